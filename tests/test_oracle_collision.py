@@ -1,0 +1,149 @@
+"""Node-level pins of the oracle step: equilibrium moments, conservation, forcing identities.
+
+These check the oracle against what the paper's equations and the mathematics
+fix, not against the oracle's own formulas: the moments of Eq. (9), the mass and
+momentum budget of a forced collision, the moments of the Guo source term, the
+scalar budget of Eqs. (11)-(17), the permutation property of streaming, and a
+second node-by-node transcription.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import lattice as lat, micro, model
+
+PAIRS = [(27, 19), (27, 7), (19, 7)]
+
+
+def _rand_state(rng, shape, lf, lg, amp=0.05):
+    f = lf.w.reshape((-1,) + (1,) * len(shape)) * (1.0 + amp * rng.uniform(-1, 1, (lf.q,) + shape))
+    g = lg.w.reshape((-1,) + (1,) * len(shape)) * (1.0 + amp * rng.uniform(-1, 1, (lg.q,) + shape))
+    return f, g
+
+
+@pytest.mark.parametrize("q", [15, 19, 27])
+def test_equilibrium_moments_through_second_order(q):
+    L = lat.BY_Q[q]
+    rng = np.random.default_rng(1)
+    rho = 1.0 + 0.1 * rng.uniform(-1, 1, 50)
+    u = 0.1 * rng.uniform(-1, 1, (3, 50))
+    feq = model.f_equilibrium(L, rho, u)
+    e = L.e.astype(float)
+    np.testing.assert_allclose(feq.sum(0), rho, rtol=1e-14)
+    np.testing.assert_allclose(np.tensordot(e.T, feq, axes=(1, 0)), rho * u, rtol=0, atol=1e-15)
+    P = np.einsum("ia,ib,in->abn", e, e, feq)
+    expect = L.cs2 * rho * np.eye(3)[:, :, None] + rho * u[:, None, :] * u[None, :, :]
+    np.testing.assert_allclose(P, expect, rtol=0, atol=1e-14)
+
+
+def test_d3q7_theta_keeps_zeroth_and_first_moment():
+    L = lat.D3Q7
+    rng = np.random.default_rng(2)
+    u = 0.1 * rng.uniform(-1, 1, (3, 40))
+    th = model.theta(L, u)
+    np.testing.assert_allclose(th.sum(0), 1.0, rtol=1e-14)
+    np.testing.assert_allclose(np.tensordot(L.e.T.astype(float), th, axes=(1, 0)), u,
+                               rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("q_f,q_g", PAIRS)
+@pytest.mark.parametrize("forcing", ["guo", "shift"])
+def test_collision_mass_momentum_budget(q_f, q_g, forcing):
+    """A forced BGK collision keeps mass and adds exactly F of momentum per node."""
+    lf, lg = lat.BY_Q[q_f], lat.BY_Q[q_g]
+    rng = np.random.default_rng(3)
+    f, g = _rand_state(rng, (64,), lf, lg)
+    U = model.raw_units(tau_f=0.5 + 0.3 * rng.uniform(), tau_g=0.55, nb=0.02, forcing=forcing)
+    fs, gs, m = model.collide(f, g, lf, lg, U)
+    e = lf.e.astype(float)
+    np.testing.assert_allclose(fs.sum(0), f.sum(0), rtol=1e-15)
+    dmom = np.tensordot(e.T, fs - f, axes=(1, 0))
+    assert np.abs(m.F[2]).max() > 1e-5
+    np.testing.assert_allclose(dmom, m.F, rtol=0, atol=2e-16)
+
+
+def test_printed_shan_chen_shift_adds_only_half_the_force():
+    """Eq. (10) as printed (tau F / (2 rho)) gains F/2 per step: the reason for the tau F / rho reading."""
+    lf, lg = lat.D3Q27, lat.D3Q19
+    f, g = _rand_state(np.random.default_rng(4), (16,), lf, lg)
+    U = dataclasses.replace(model.raw_units(0.7, 0.6, nb=0.02, forcing="shift"), shift_half=True)
+    fs, _, m = model.collide(f, g, lf, lg, U)
+    dmom = np.tensordot(lf.e.T.astype(float), fs - f, axes=(1, 0))
+    np.testing.assert_allclose(dmom, 0.5 * m.F, rtol=0, atol=2e-16)
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_guo_source_moments(q):
+    """sum F_i = 0, sum e_i F_i = (1 - 1/(2 tau)) F, second moment = (1 - 1/(2 tau))(uF + Fu)."""
+    L = lat.BY_Q[q]
+    rng = np.random.default_rng(5)
+    u = 0.1 * rng.uniform(-1, 1, (3, 30))
+    F = 1e-3 * rng.uniform(-1, 1, (3, 30))
+    tau = 0.73
+    Fi = model.guo_source(L, tau, u, F)
+    a = 1.0 - 1.0 / (2.0 * tau)
+    e = L.e.astype(float)
+    np.testing.assert_allclose(Fi.sum(0), 0.0, atol=1e-18)
+    np.testing.assert_allclose(np.tensordot(e.T, Fi, axes=(1, 0)), a * F, rtol=1e-13, atol=1e-19)
+    M2 = np.einsum("ia,ib,in->abn", e, e, Fi)
+    expect = a * (u[:, None] * F[None, :] + F[:, None] * u[None, :])
+    np.testing.assert_allclose(M2, expect, rtol=1e-12, atol=1e-18)
+
+
+@pytest.mark.parametrize("q_f,q_g", PAIRS)
+@pytest.mark.parametrize("forcing", ["guo", "shift"])
+def test_scalar_budget_gains_exactly_the_source(q_f, q_g, forcing):
+    """Under the Chai-Zhao reading sum_j g*_j - sum_j g_j = s at every node (Eqs. (11), (16)-(17))."""
+    lf, lg = lat.BY_Q[q_f], lat.BY_Q[q_g]
+    f, g = _rand_state(np.random.default_rng(6), (40,), lf, lg)
+    U = model.raw_units(0.62, 0.6, nb=0.03, forcing=forcing)
+    fs, gs, m = model.collide(f, g, lf, lg, U)
+    assert np.abs(m.s).max() > 1e-6
+    # sum g is ~1, so the difference carries a few FP64 ulps of 1 (2.2e-16 each)
+    np.testing.assert_allclose(gs.sum(0) - g.sum(0), m.s, rtol=0, atol=2e-15)
+
+
+def test_uniform_flow_is_a_fixed_point():
+    lf, lg = lat.D3Q27, lat.D3Q19
+    shape = (4, 4, 4)
+    u = np.zeros((3,) + shape)
+    u[0], u[1], u[2] = 0.03, -0.02, 0.01
+    rho = np.full(shape, 1.01)
+    f = model.f_equilibrium(lf, rho, u)
+    g = 1.0 * model.theta(lg, u)
+    U = model.raw_units(0.55, 0.6, nb=0.0)   # G = 0: no force, no source
+    fs, gs, _ = model.collide(f, g, lf, lg, U)
+    np.testing.assert_allclose(fs, f, rtol=1e-14)
+    np.testing.assert_allclose(gs, g, rtol=1e-14)
+    np.testing.assert_array_equal(model.stream(fs, lf), fs)
+
+
+@pytest.mark.parametrize("q", [7, 15, 19, 27])
+def test_streaming_is_a_permutation_with_period_n(q):
+    L = lat.BY_Q[q]
+    rng = np.random.default_rng(7)
+    a = rng.standard_normal((q, 5, 5, 5))
+    b = a.copy()
+    for _ in range(5):
+        b = model.stream(b, L)
+    np.testing.assert_array_equal(a, b)                 # bit-exact return after n steps
+    one = model.stream(a, L)
+    for i in range(q):                                  # a single step moves by +e_i
+        ex, ey, ez = L.e[i]
+        assert one[i, ez % 5, ey % 5, ex % 5] == a[i, 0, 0, 0]
+    assert sorted(one.ravel()) == sorted(a.ravel())
+
+
+@pytest.mark.parametrize("q_f,q_g", PAIRS)
+@pytest.mark.parametrize("forcing", ["guo", "shift"])
+def test_vectorised_step_matches_node_by_node_transcription(q_f, q_g, forcing):
+    lf, lg = lat.BY_Q[q_f], lat.BY_Q[q_g]
+    rng = np.random.default_rng(8)
+    f, g = _rand_state(rng, (3, 4, 5), lf, lg, amp=0.1)
+    U = model.raw_units(0.507, 0.53, nb=0.04, forcing=forcing)
+    fs, gs, _ = model.collide(f, g, lf, lg, U)
+    fv, gv = model.stream(fs, lf), model.stream(gs, lg)
+    fm, gm = micro.step(f.tolist(), g.tolist(), q_f, q_g, U.tau_f, U.tau_g, U.G, U.beta, forcing)
+    np.testing.assert_allclose(np.array(fm), fv, rtol=1e-14, atol=0)
+    np.testing.assert_allclose(np.array(gm), gv, rtol=1e-14, atol=0)
