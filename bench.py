@@ -1,0 +1,235 @@
+#!/usr/bin/env python
+"""Throughput of the stratified Taylor-Green D3Q27 x D3Q19 DDF lattice Boltzmann step on one MI355X.
+
+Workload (default): 256^3 periodic box, D3Q27 momentum x D3Q19 scalar lattice,
+Shan-Chen velocity-shift buoyancy, Re 1600, Fr 1, Sc 0.7, U0 0.05, FP32
+populations in the AA in-place layout, energy / dissipation diagnostics every
+16 steps (~ t_c / 50), synthetic Taylor-Green initial state with 1e-6 seeded
+density noise.  One "step" = one fused stream-collide-force launch (plus, on
+diagnostic steps, the dissipation stencil and the final reduction).
+
+Prints ONE JSON line: MLUPS (whole job), ms per step, the roofline of the step
+kernel (algorithmic bytes 2 (Q_f + Q_g) b per node over its HIP-event-timed
+average duration, against the 8 TB/s HBM peak), the streaming-copy ceiling,
+the HBM traffic read from the committed rocprofv3 counter summary when it was
+taken on the current kernel sources, the FP64 oracle timed on the host cores,
+and the energy error of the GPU against the oracle on the 32^3 parity case.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+PEAK_HBM_GBS = 8000.0
+
+
+def kernel_source_hash():
+    csrc = os.path.join(ROOT, "paper_2605_14505_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(f.encode())
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(workload_key, n3, bytes_per_node):
+    """HBM bytes per launch from profiles/<key>_counters.txt if its source hash is current."""
+    path = os.path.join(ROOT, "profiles", f"{workload_key}_counters.txt")
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_hash") != kernel_source_hash():
+        return None, "counters predate the current kernel sources"
+    try:
+        return float(kv["hbm_bytes_per_launch"]), path
+    except (KeyError, ValueError):
+        return None, "malformed counter summary"
+
+
+def cpu_baseline(n, steps, forcing):
+    """The FP64 oracle as it stands, single-threaded BLAS, on a bounded sample of the workload."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import lattice as lat, model
+    p = model.Params(n=n, q_f=27, q_g=19, forcing=forcing, u0=0.05, re=1600.0, fr=1.0, sc=0.7,
+                     noise_amp=1e-6, seed=0)
+    with threadpool_limits(limits=1):
+        U = model.units(p)
+        lf, lg = lat.BY_Q[27], lat.BY_Q[19]
+        f, g = model.init_tgv(p)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fs, gs, _ = model.collide(f, g, lf, lg, U)
+            f, g = model.stream(fs, lf), model.stream(gs, lg)
+        dt = time.perf_counter() - t0
+    del f, g
+    return {"value": round(n ** 3 * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{steps} steps of the same stratified-TGV D3Q27x19 {forcing} step on a {n}^3 box "
+                      f"(the 256^3 box needs 25 GB and ~4 min per oracle step), NumPy FP64, one "
+                      f"thread, {dt:.1f} s"}
+
+
+def energy_error(stgv, forcing):
+    """Max relative error of E_k, E_p, eps_k, eps_p of the GPU against the oracle on the 32^3 case."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import model
+    kw = dict(n=32, q_f=27, q_g=19, forcing=forcing, u0=0.05, re=800.0, fr=1.0, sc=1.0,
+              g_over_n=1.0, noise_amp=1e-6, seed=0)
+    with threadpool_limits(limits=1):
+        _, ser = model.run(model.Params(**kw), 201, diag_every=20)
+    sim = stgv.Simulation(diag_every=20, **kw)
+    sim.step(201)
+    recs = sim.diagnostics()
+    sim.close()
+    out = {}
+    for key in ("ek", "ep", "eps_k", "eps_p"):
+        out[key] = max(abs(r[key] - getattr(d, key)) / abs(getattr(d, key))
+                       for r, d in zip(recs, ser) if getattr(d, key) != 0.0)
+    return {"workload": "32^3 D3Q27x19, Re 800, Pr 1, Fr 1, 200 steps, records every 20",
+            **{k: float(f"{v:.3e}") for k, v in out.items()}}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=600)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--q-f", type=int, default=27)
+    ap.add_argument("--q-g", type=int, default=19)
+    ap.add_argument("--forcing", default="shift", choices=["guo", "shift"])
+    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16"])
+    ap.add_argument("--compute", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--diag-every", type=int, default=16)
+    ap.add_argument("--cpu-sample-n", type=int, default=128)
+    ap.add_argument("--cpu-sample-steps", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-energy-error", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs the single-GPU step only: the halo-exchange path across GPUs is not "
+              "part of this build (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    sys.path.insert(0, ROOT)
+    from paper_2605_14505_amd import stgv
+
+    n, K, W = args.n, args.steps, args.warmup
+    n3 = n ** 3
+    bpe = 4 if args.storage == "fp32" else 2
+    bytes_per_node = 2 * (args.q_f + args.q_g) * bpe
+    common = dict(n=n, q_f=args.q_f, q_g=args.q_g, forcing=args.forcing, storage=args.storage,
+                  compute=args.compute, u0=0.05, re=1600.0, fr=1.0, sc=0.7, g_over_n=1.0,
+                  noise_amp=1e-6, seed=0)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+
+    # ---- whole-job throughput: K steps with diagnostics at the production cadence
+    sim = stgv.Simulation(diag_every=args.diag_every, **common)
+    sim.step(W)
+    torch.cuda.synchronize()
+    sim.diagnostics(raise_unstable=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(K)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    recs = sim.diagnostics(raise_unstable=False)
+    finite = all(r["nonfinite"] == 0 for r in recs)
+    sim.close()
+    del sim
+    mlups = n3 * K / wall / 1e6
+
+    # ---- the step kernel alone, HIP events on the launch stream
+    sim = stgv.Simulation(diag_every=0, **common)
+    sim.step(W)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    sim.step(K)
+    ev1.record(stream)
+    ev1.synchronize()
+    kernel_ms = ev0.elapsed_time(ev1) / K
+    sim.close()
+    del sim
+    achieved = bytes_per_node * n3 / (kernel_ms * 1e-3) / 1e9
+
+    # ---- streaming-copy ceiling on buffers of the same size as the state
+    nbytes = min(2 << 30, (args.q_f + args.q_g) * n3 * bpe)
+    nbytes -= nbytes % 16
+    a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    b = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    for _ in range(3):
+        stgv.lbm_bw_probe(0, b, a, nbytes, stream.cuda_stream)
+    ev0.record(stream)
+    reps = 20
+    for _ in range(reps):
+        stgv.lbm_bw_probe(0, b, a, nbytes, stream.cuda_stream)
+    ev1.record(stream)
+    ev1.synchronize()
+    copy_gbs = 2 * nbytes * reps / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    del a, b
+
+    key = f"step_{n}_{args.q_f}x{args.q_g}_{args.storage}_{args.compute}_{args.forcing}"
+    traffic, traffic_src = read_traffic(key, n3, bytes_per_node)
+
+    out = {
+        "metric": "MLUPS + % HBM roofline per D3Q27x19 step at 256^3; energy error vs FP64 oracle",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(wall / K * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.compute == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"stratified Taylor-Green vortex, {n}^3 periodic box, D3Q{args.q_f}xD3Q{args.q_g}, "
+                        f"{'velocity-shift' if args.forcing == 'shift' else 'Guo source-term'} buoyancy, "
+                        f"{args.storage} populations (AA in place), {args.compute} arithmetic, "
+                        f"diagnostics every {args.diag_every} steps",
+            "n": n, "q_f": args.q_f, "q_g": args.q_g, "re": 1600, "fr": 1.0, "sc": 0.7, "u0": 0.05,
+            "storage": args.storage, "compute": args.compute, "diag_every": args.diag_every,
+            "finite": finite,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": traffic,
+            "kernel": "lbm_step_kernel",
+            "kernel_ms": round(kernel_ms, 5),
+            "bytes_per_node": bytes_per_node,
+            "step_mlups": round(n3 / (kernel_ms * 1e-3) / 1e6, 1),
+            "copy_ceiling_gbs": round(copy_gbs, 1),
+            "frac_of_copy": round(achieved / copy_gbs, 4),
+            "traffic_source": traffic_src,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample_n, args.cpu_sample_steps, args.forcing)
+        out["cpu_baseline"]["host_threads_available"] = os.cpu_count()
+    if not args.no_energy_error:
+        out["energy_error"] = energy_error(stgv, args.forcing)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,175 @@
+/*
+ * stgv.h - C ABI of the MI355X (gfx950) stratified Taylor-Green double-
+ * distribution-function lattice Boltzmann step.
+ *
+ * The method is the paper's Section 2: a D3Q<q_f> momentum lattice f (LBE
+ * Eq. (5), moments Eqs. (6)-(7), BGK Eq. (8), equilibrium Eq. (9)) coupled to a
+ * D3Q<q_g> scalar lattice g for the density perturbation rho' (LBE Eq. (11),
+ * source Eqs. (12)-(13), BGK Eq. (14), equilibrium Eq. (15), zeroth moment
+ * Eqs. (16)-(17)) through the Boussinesq force F = (0, 0, -G rho') (Eq. (18)),
+ * applied by the Guo source term or the Shan-Chen velocity shift (Eq. (10)),
+ * on the periodic box [0, 2 pi)^3 (Section 2.4) with the Taylor-Green initial
+ * state of Eqs. (20)-(21) and the energy / dissipation diagnostics of
+ * Eqs. (22)-(26).  Stencils are those of Table 1.
+ *
+ * Conventions shared by every call:
+ *  - Memory: the caller allocates and owns every device buffer and the HIP
+ *    stream.  A context keeps non-owning pointers, which must stay valid until
+ *    lbm_destroy.  lbm_destroy frees host memory only.
+ *  - Errors: every int-returning call returns an lbm_status and never aborts
+ *    or throws.  lbm_last_error(ctx) (or lbm_last_error(NULL) for calls that
+ *    failed before a context existed) gives a message.  Parameter errors are
+ *    reported before any device work is queued.
+ *  - Streams: all device work is queued on the caller's stream, in order.
+ *    lbm_diagnostics, lbm_read_fields, lbm_read_populations and
+ *    lbm_load_populations synchronise that stream before they return.
+ *  - Threading: one host thread per context at a time.
+ *  - Determinism: identical parameters give bit-identical populations and
+ *    diagnostics (fixed-order FP64 reductions, no atomics).
+ *  - Units: lattice units (dx = dt = 1) inside; lbm_diag reports the paper's
+ *    non-dimensional values (E / U^2, eps L / U^3, t = step U / L) with
+ *    L = n / (2 pi) nodes per unit length and U = u0.
+ */
+#ifndef STGV_H
+#define STGV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx; /* opaque, host side */
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,    /* invalid parameter or argument (nothing was queued) */
+  LBM_ESIZE = -2,     /* a buffer is smaller than lbm_query_sizes requires */
+  LBM_EHIP = -3,      /* a HIP call failed; the message carries hipGetErrorString */
+  LBM_EUNSTABLE = -4, /* a drained diagnostic record is non-finite or has max|u| > c_s */
+  LBM_ESTATE = -5     /* call not valid in the current state (e.g. diagnostics ring full) */
+} lbm_status;
+
+typedef enum {
+  LBM_FORCE_GUO = 0,  /* Guo-Zheng-Shi discrete source term (cited with Eq. (5)) */
+  LBM_FORCE_SHIFT = 1 /* Shan-Chen velocity shift u_eq = u' + tau_f F / rho (Eq. (10)) */
+} lbm_forcing;
+
+typedef enum {
+  LBM_FP32 = 0,       /* populations stored as FP32 deviations f_i - w_i */
+  LBM_FP16 = 1,       /* ... as IEEE half deviations, round-to-nearest-even */
+  LBM_BF16 = 2        /* ... as bfloat16 deviations, round-to-nearest-even */
+} lbm_storage;
+
+typedef enum {
+  LBM_COMPUTE_FP32 = 0, /* collision and forcing arithmetic in FP32 (every storage type) */
+  LBM_COMPUTE_FP64 = 1  /* ... in FP64 (FP32 storage only) */
+} lbm_compute;
+
+typedef enum {
+  LBM_LAYOUT_AA = 0,  /* one population array, AA in-place streaming */
+  LBM_LAYOUT_AB = 1   /* two population arrays (push), for cross-checks */
+} lbm_layout;
+
+/* Problem statement (Section 2.4: Re_0 = U L / nu, Fr_0 = U / (N L), Sc = nu / D). */
+typedef struct {
+  int32_t n;           /* periodic box n^3 nodes, 4 <= n <= 1024 */
+  int32_t q_f, q_g;    /* stencil pair D3Q{q_f} x D3Q{q_g}: (27,19), (27,7) or (19,7) */
+  int32_t forcing;     /* lbm_forcing */
+  int32_t storage;     /* lbm_storage */
+  int32_t compute;     /* lbm_compute */
+  int32_t layout;      /* lbm_layout */
+  int32_t diag_every;  /* a diagnostic record every k steps (at steps 0, k, 2k, ...); 0 = none */
+  int32_t pad;         /* extra elements between population arrays; < 0 = library default */
+  int32_t reserved;    /* must be 0 */
+  double u0;           /* Taylor-Green amplitude U in lattice units, 0 < u0 < 0.3 */
+  double re;           /* Re_0 > 0 */
+  double fr;           /* Fr_0 > 0; +inf = unstratified (G = 0) */
+  double sc;           /* Sc > 0 (Pr for a thermal scalar) */
+  double g_over_n;     /* G / N > 0: split of N^2 between G and d rho_b / dz (rho_0 = 1) */
+  double noise_amp;    /* rho'(t=0) = A (2 xi - 1), xi uniform from SplitMix64; A >= 0 */
+  uint64_t seed;       /* key of the noise: xi(node) = splitmix64(seed * 2^40 + x + n (y + n z)) */
+} lbm_params;
+
+/* One diagnostic record, in the paper's non-dimensional units. */
+typedef struct {
+  int64_t step;        /* time step the moments belong to (pre-collision state of that step) */
+  double t;            /* step * U / L */
+  double ek;           /* Eq. (22) / U^2 */
+  double ep;           /* Eq. (23) / U^2 (0 when G = 0) */
+  double eps_k;        /* Eq. (25) * L / U^3, central differences */
+  double eps_p;        /* Eq. (26) * L / U^3 (0 when G = 0) */
+  double mass;         /* sum over nodes of rho */
+  double scalar;       /* sum over nodes and directions of g */
+  double mom[3];       /* sum over nodes of rho u (lattice units) */
+  double umax;         /* max |u| (lattice units) */
+  int64_t nonfinite;   /* nodes with a non-finite rho, |u|^2 or rho' */
+} lbm_diag;
+
+/* Validate parameters and report the device bytes the caller must provide:
+ * pop_bytes for the populations, work_bytes for fields, partial sums and the
+ * diagnostics ring.  CPU only: touches no device.  Returns LBM_EINVAL with a
+ * message for any invalid parameter. */
+int lbm_query_sizes(const lbm_params* p, size_t* pop_bytes, size_t* work_bytes);
+
+/* Derived lattice constants (Eqs. (8), (13), (14), (19)) as 8 doubles:
+ * [L, nu, D, tau_f, tau_g, N, G, beta] with beta = (d rho_b/dz)_LU.  CPU only. */
+int lbm_derived(const lbm_params* p, double* out8);
+
+/* Create a context and queue the Taylor-Green initial state (Eqs. (20)-(21),
+ * pure equilibrium, rho'(0) = seeded noise) on `hip_stream` (a hipStream_t,
+ * NULL = default stream).  pop_dev / work_dev: device buffers of at least
+ * lbm_query_sizes bytes, 256-byte aligned, owned by the caller.  On success
+ * *out receives the context and the step counter is 0. */
+int lbm_init_tgv(const lbm_params* p, void* pop_dev, size_t pop_bytes, void* work_dev,
+                 size_t work_bytes, void* hip_stream, lbm_ctx** out);
+
+/* Queue n >= 0 fused stream-collide-force steps.  A step whose index is a
+ * multiple of diag_every also queues its diagnostic record.  Returns
+ * LBM_ESTATE without queueing anything if the records would overflow the
+ * ring (4096 records); drain it with lbm_diagnostics. */
+int lbm_step(lbm_ctx* ctx, int64_t n);
+
+/* Queue a diagnostic record of the current state (without stepping). */
+int lbm_sample(lbm_ctx* ctx);
+
+/* Synchronise the stream and move up to `max` pending records, oldest first,
+ * into out[0..*n_out).  Returns LBM_EUNSTABLE if any returned record is
+ * non-finite or has max|u| above the lattice speed of sound. */
+int lbm_diagnostics(lbm_ctx* ctx, lbm_diag* out, int32_t max, int32_t* n_out);
+
+/* Write the current moments as five FP32 device arrays of n^3 values, x
+ * fastest: rho - 1, u_x, u_y, u_z (physical velocity, Eq. (7)), rho'
+ * (Eq. (16)).  dev_out must hold 5 n^3 floats.  Synchronises. */
+int lbm_read_fields(lbm_ctx* ctx, float* dev_out);
+
+/* Write the current pre-collision populations as FP32 deviations in natural
+ * order: (q_f + q_g) arrays of n^3 values (f_i - w_i, then g_j - w^g_j),
+ * whatever the layout and step parity.  Synchronises. */
+int lbm_read_populations(lbm_ctx* ctx, float* dev_out);
+
+/* Replace the state by the populations in dev_in (same layout as
+ * lbm_read_populations, rounded to the storage type) and set the step
+ * counter to `step`.  Synchronises. */
+int lbm_load_populations(lbm_ctx* ctx, const float* dev_in, int64_t step);
+
+/* Velocity set of D3Q{q}, q in {7, 15, 19, 27} (Table 1, in this library's
+ * order): e[3 q] as (x, y, z) triples, w[q], *cs2.  CPU only. */
+int lbm_stencil_info(int32_t q, int32_t* e, double* w, double* cs2);
+
+/* Streaming-bandwidth probe: kind 0 copies `bytes` from src to dst, kind 1
+ * reads src (one float per block written to dst), kind 2 writes dst.
+ * Queued on hip_stream; bytes must be a multiple of 16. */
+int lbm_bw_probe(int32_t kind, void* dst, const void* src, size_t bytes, void* hip_stream);
+
+int64_t lbm_get_step(const lbm_ctx* ctx);
+const char* lbm_last_error(const lbm_ctx* ctx);
+const char* lbm_status_string(int status);
+void lbm_destroy(lbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STGV_H */

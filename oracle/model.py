@@ -32,7 +32,8 @@ listed in the design notes):
   explicit order: rho' needs S, F needs rho').
 * Theta in Eq. (15) uses the same equilibrium velocity as f^eq, with the scalar
   stencil's own weights and c_s^2.
-* rho_0 = 1 and G = (G/N) N with G/N = 1, so beta = (d rho_b/dz)_LU = -N^2/G.
+* rho_0 = 1 and G = (G/N) N with G/N a parameter (default 1), so
+  beta = (d rho_b/dz)_LU = -N^2/G; only N^2 enters the incompressible dynamics.
 * initial pressure p0 = (rho_0 U^2/16)(cos 2x + cos 2y)(cos 2z + 2) (the Brachet
   form; the printed cos(2z+2) is garbled), rho = rho_0 + p0/c_s^2, pure
   equilibrium populations, nodes at x_j = 2 pi j / N.
@@ -223,34 +224,61 @@ def splitmix64(x):
         return z ^ (z >> np.uint64(31))
 
 
-def noise(n, amp, seed):
+def noise_at(idx, amp, seed):
     """rho'(t=0) = A (2 xi - 1), xi = (splitmix64(seed 2^40 + idx) >> 11) 2^-53, idx = x + n(y + n z)."""
-    idx = np.arange(n * n * n, dtype=np.uint64)
+    idx = np.asarray(idx, dtype=np.uint64)
     with np.errstate(over="ignore"):
         ctr = np.uint64((seed << 40) & M64) + idx
     xi = (splitmix64(ctr) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
-    return (amp * (2.0 * xi - 1.0)).reshape(n, n, n)
+    return amp * (2.0 * xi - 1.0)
 
 
-def tgv_fields(n, u0):
-    """Velocity Eq. (20) and density rho0 + p0/c_s^2 on nodes x_j = 2 pi j / n, arrays [z, y, x]."""
-    x = 2.0 * math.pi * np.arange(n) / n
-    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
-    u = np.stack([u0 * np.sin(X) * np.cos(Y) * np.cos(Z),
-                  -u0 * np.cos(X) * np.sin(Y) * np.cos(Z),
-                  np.zeros_like(X)])
-    p0 = RHO0 * u0 * u0 / 16.0 * (np.cos(2 * X) + np.cos(2 * Y)) * (np.cos(2 * Z) + 2.0)
+def noise(n, amp, seed):
+    return noise_at(np.arange(n * n * n, dtype=np.uint64), amp, seed).reshape(n, n, n)
+
+
+def tgv_fields_at(X, Y, Z, n, u0):
+    """Velocity Eq. (20) and pressure (Eq. (21) as read) at integer node indices, nodes x_j = 2 pi j / n."""
+    h = 2.0 * math.pi / n
+    x, y, z = h * X, h * Y, h * Z
+    u = np.stack([u0 * np.sin(x) * np.cos(y) * np.cos(z),
+                  -u0 * np.cos(x) * np.sin(y) * np.cos(z),
+                  np.zeros(np.shape(x))])
+    p0 = RHO0 * u0 * u0 / 16.0 * (np.cos(2 * x) + np.cos(2 * y)) * (np.cos(2 * z) + 2.0)
     return u, p0
 
 
-def init_tgv(p: Params):
+def tgv_fields(n, u0):
+    """Velocity and pressure on the whole grid, arrays [z, y, x]."""
+    j = np.arange(n)
+    Z, Y, X = np.meshgrid(j, j, j, indexing="ij")
+    return tgv_fields_at(X, Y, Z, n, u0)
+
+
+def _tgv_populations(p: Params, X, Y, Z):
     lf, lg = lat.BY_Q[p.q_f], lat.BY_Q[p.q_g]
-    u, p0 = tgv_fields(p.n, p.u0)
+    u, p0 = tgv_fields_at(X, Y, Z, p.n, p.u0)
     rho = RHO0 + p0 / lf.cs2
-    rho_p = noise(p.n, p.noise_amp, p.seed)
-    f = f_equilibrium(lf, rho, u)
-    g = (rho_p + RHO0) * theta(lg, u)
-    return f, g
+    idx = X.astype(np.uint64) + np.uint64(p.n) * (Y.astype(np.uint64) + np.uint64(p.n) * Z.astype(np.uint64))
+    rho_p = noise_at(idx, p.noise_amp, p.seed)
+    return f_equilibrium(lf, rho, u), (rho_p + RHO0) * theta(lg, u)
+
+
+def init_tgv_patch(p: Params, center, radius):
+    """TGV populations on the (2r+1)^3 nodes around center = (z, y, x), wrapped periodically.
+
+    Stepping such a patch s <= r times with periodic streaming leaves its centre
+    node exact: wrong values enter from the patch faces one node per step."""
+    offs = np.arange(-radius, radius + 1)
+    cz, cy, cx = center
+    Z, Y, X = np.meshgrid((cz + offs) % p.n, (cy + offs) % p.n, (cx + offs) % p.n, indexing="ij")
+    return _tgv_populations(p, X, Y, Z)
+
+
+def init_tgv(p: Params):
+    j = np.arange(p.n)
+    Z, Y, X = np.meshgrid(j, j, j, indexing="ij")
+    return _tgv_populations(p, X, Y, Z)
 
 
 # ----------------------------------------------------------------------------
@@ -314,19 +342,55 @@ def dissipation_series(ts, energies):
 
 
 # ----------------------------------------------------------------------------
+# Storage precision of the populations (the FP16 / BF16 / FP32 storage forms)
+# ----------------------------------------------------------------------------
+def round_to_bf16(x):
+    """Round to the nearest bfloat16 (8-bit significand), ties to even, in one rounding."""
+    x = np.asarray(x, dtype=np.float64)
+    m, e = np.frexp(x)                        # x = m 2^e, 0.5 <= |m| < 1
+    return np.ldexp(np.round(m * 256.0) / 256.0, e)
+
+
+def round_storage(x, kind):
+    """Round population deviations to the storage type `kind` and return them as FP64."""
+    if kind is None or kind == "fp64":
+        return x
+    if kind == "fp32":
+        return x.astype(np.float32).astype(np.float64)
+    if kind == "fp16":
+        return x.astype(np.float16).astype(np.float64)
+    if kind == "bf16":
+        return round_to_bf16(x)
+    raise ValueError(kind)
+
+
+def store(pop, L, kind):
+    """Populations whose deviations from the weights are held in `kind` (the arithmetic stays FP64)."""
+    if kind is None or kind == "fp64":
+        return pop
+    w = L.w.reshape((-1,) + (1,) * (pop.ndim - 1))
+    return w + round_storage(pop - w, kind)
+
+
+# ----------------------------------------------------------------------------
 # Driver
 # ----------------------------------------------------------------------------
-def run(p: Params, steps, diag_every=0, state=None, U: Units = None, **kw):
-    """Advance `steps` steps from the TGV state (or `state`); returns ((f, g), [Diag])."""
+def run(p: Params, steps, diag_every=0, state=None, U: Units = None, storage=None, **kw):
+    """Advance `steps` steps from the TGV state (or `state`); returns ((f, g), [Diag]).
+
+    storage: None (FP64 throughout) or "fp32" / "fp16" / "bf16": the population
+    deviations are rounded to that type after initialisation and after every
+    step, the storage forms of the populations with FP64 arithmetic."""
     lf, lg = lat.BY_Q[p.q_f], lat.BY_Q[p.q_g]
     U = U or units(p, **kw)
     f, g = state if state is not None else init_tgv(p)
+    f, g = store(f, lf, storage), store(g, lg, storage)
     series = []
     for n in range(steps):
         fs, gs, m = collide(f, g, lf, lg, U)
         if diag_every and n % diag_every == 0:
             series.append(diagnostics(m, U, n))
-        f, g = stream(fs, lf), stream(gs, lg)
+        f, g = store(stream(fs, lf), lf, storage), store(stream(gs, lg), lg, storage)
     return (f, g), series
 
 

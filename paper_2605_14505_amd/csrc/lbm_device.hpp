@@ -1,0 +1,362 @@
+// Device code of the fused stream-collide-force step (gfx950).
+//
+// One thread owns one lattice node.  Populations are stored as deviations from
+// their lattice weights (df_i = f_i - w_i, dg_j = g_j - w^g_j), structure of
+// arrays: array i holds df_i for every node, x fastest, arrays `stride`
+// elements apart; the Q_f momentum arrays come first, then the Q_g scalar
+// arrays.  All collision and forcing arithmetic is FP32 on the deviations (no
+// "1 -" cancellation); storage is FP32, FP16 or BF16.
+//
+// Streaming (LHS of Eqs. (5) and (11), periodic box) uses the AA in-place
+// pattern: an even step reads slot i of its own node and writes the
+// post-collision value into slot opp(i) of the same node; an odd step reads
+// slot opp(i) at x - e_i and writes slot i at x + e_i.  Both touch exactly the
+// same addresses a thread reads, so the update is race-free in place.  After
+// an even number of steps the array is in natural (pre-collision, streamed)
+// order.  MODE_AB is a two-lattice push variant (read natural at x, write
+// natural at x + e_i into a second array) kept for bitwise cross-checking.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "stencil.hpp"
+
+namespace stgv {
+
+enum Mode : int { MODE_EVEN = 0, MODE_ODD = 1, MODE_AB = 2 };
+enum Forcing : int { FORCE_GUO = 0, FORCE_SHIFT = 1 };
+enum KernelFlags : int {
+  K_COLLIDE = 1,    // collide and stream (the time step)
+  K_FIELDS = 2,     // write rho - 1, u_x, u_y, u_z, rho' per node
+  K_PARTIALS = 4,   // write per-block diagnostic partials
+};
+
+// Per-block diagnostic partials written by the diagnostic step / moments kernels.
+enum Partial : int {
+  P_EK = 0,     // sum 1/2 |u|^2
+  P_EP,         // sum 1/2 ((G/N) rho')^2
+  P_DRHO,       // sum (rho - 1)
+  P_DSIG,       // sum (sum_j g_j - 1)
+  P_MX, P_MY, P_MZ,  // sum rho u
+  P_UMAX2,      // max |u|^2
+  P_NONFINITE,  // count of nodes with a non-finite moment
+  NPART
+};
+enum FdPartial : int { FD_CURL2 = 0, FD_GRAD2, NFD };
+
+// Record layout in the device diagnostics ring (doubles).
+enum Record : int {
+  R_STEP = 0, R_EK, R_EP, R_CURL2, R_GRAD2, R_DRHO, R_DSIG, R_MX, R_MY, R_MZ, R_UMAX2,
+  R_NONFINITE, NREC = 16
+};
+
+struct PhysConsts {
+  double omega_f;     // 1 / tau_f
+  double omega_g;     // 1 / tau_g
+  double tau_f;       // Shan-Chen shift
+  double G;           // Boussinesq gravity (lattice units)
+  double beta;        // (d rho_b / dz)_LU
+  double g_over_n;    // G / N for the potential energy
+};
+
+struct Geometry {
+  int n;             // box edge
+  int64_t stride;    // elements between population arrays
+};
+
+// ---------------------------------------------------------------------------
+// storage <-> compute conversion (compute type C is float or double)
+// ---------------------------------------------------------------------------
+struct bf16_t { uint16_t bits; };
+
+template <typename C> __device__ __forceinline__ C load_as(const float* p) { return (C)(*p); }
+template <typename C> __device__ __forceinline__ C load_as(const _Float16* p) { return (C)(float)(*p); }
+template <typename C> __device__ __forceinline__ C load_as(const bf16_t* p) {
+  return (C)__uint_as_float(((uint32_t)p->bits) << 16);
+}
+
+__device__ __forceinline__ uint16_t float_to_bf16_rne(float v) {
+  uint32_t u = __float_as_uint(v);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+// Rounding to the storage type is round-to-nearest-even in every case (a double
+// is rounded once, straight to FP32; FP16 / BF16 stores take FP32 values).
+__device__ __forceinline__ void store_as(float* p, float v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void store_as(float* p, double v) { __builtin_nontemporal_store((float)v, p); }
+__device__ __forceinline__ void store_as(_Float16* p, float v) { __builtin_nontemporal_store((_Float16)v, p); }
+__device__ __forceinline__ void store_as(bf16_t* p, float v) {
+  __builtin_nontemporal_store(float_to_bf16_rne(v), &p->bits);
+}
+
+// ---------------------------------------------------------------------------
+// neighbour addressing on the periodic box
+//
+// Per-thread offsets are 32-bit node indices (n^3 * element size < 2^32); the
+// base of each population array is uniform across the wavefront, so a load is
+// a scalar base plus a 32-bit vector offset and the per-node state costs no
+// 64-bit address registers.
+// ---------------------------------------------------------------------------
+struct NodeIndex {
+  uint32_t base;                // linear index x + n (y + n z)
+  uint32_t xo[3], yo[3], zo[3]; // x -/0/+ 1, n (y -/0/+ 1), n^2 (z -/0/+ 1)
+  __device__ __forceinline__ uint32_t at(int dx, int dy, int dz) const {
+    return xo[dx + 1] + yo[dy + 1] + zo[dz + 1];
+  }
+};
+
+__device__ __forceinline__ NodeIndex make_index(int x, int y, int z, int n) {
+  NodeIndex ix;
+  const uint32_t un = (uint32_t)n, n2 = un * un;
+  ix.xo[0] = x == 0 ? un - 1 : x - 1;
+  ix.xo[1] = x;
+  ix.xo[2] = x == n - 1 ? 0 : x + 1;
+  ix.yo[0] = un * (y == 0 ? un - 1 : y - 1);
+  ix.yo[1] = un * y;
+  ix.yo[2] = un * (y == n - 1 ? 0 : y + 1);
+  ix.zo[0] = n2 * (z == 0 ? un - 1 : z - 1);
+  ix.zo[1] = n2 * z;
+  ix.zo[2] = n2 * (z == n - 1 ? 0 : z + 1);
+  ix.base = ix.xo[1] + ix.yo[1] + ix.zo[1];
+  return ix;
+}
+
+template <typename T>
+__device__ __forceinline__ const T* at_node(const T* array, uint32_t node) {
+  return (const T*)((const char*)array + node * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ T* at_node(T* array, uint32_t node) {
+  return (T*)((char*)array + node * (uint32_t)sizeof(T));
+}
+
+// Gather the pre-collision populations of one lattice (Q directions starting at
+// array `first`) in the layout given by MODE.
+template <int Q, typename T, int MODE, typename C>
+__device__ __forceinline__ void gather(C* v, const T* pop, int first, const NodeIndex& ix,
+                                       int64_t stride) {
+  using S = Stencil<Q>;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    uint32_t off;
+    int slot;
+    if (MODE == MODE_ODD) {          // post-collision value of x - e_i sits in slot opp(i)
+      off = ix.at(-S::ex[i], -S::ey[i], -S::ez[i]);
+      slot = opp(i);
+    } else {                         // natural order
+      off = ix.base;
+      slot = i;
+    }
+    v[i] = load_as<C>(at_node(pop + (int64_t)(first + slot) * stride, off));
+  }
+}
+
+// Scatter post-collision populations for MODE (AB writes into `dst`).
+template <int Q, typename T, int MODE, typename C>
+__device__ __forceinline__ void scatter(const C* v, T* dst, int first, const NodeIndex& ix,
+                                        int64_t stride) {
+  using S = Stencil<Q>;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    uint32_t off;
+    int slot;
+    if (MODE == MODE_EVEN) {         // keep at x, swapped into slot opp(i)
+      off = ix.base;
+      slot = opp(i);
+    } else {                         // odd / AB push: natural slot i at x + e_i
+      off = ix.at(S::ex[i], S::ey[i], S::ez[i]);
+      slot = i;
+    }
+    store_as(at_node(dst + (int64_t)(first + slot) * stride, off), v[i]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// node-local physics
+// ---------------------------------------------------------------------------
+// Moments over a lattice whose directions come in opposite pairs (i, i + 1):
+// sum a_i = a_0 + sum_pairs (a_i + a_{i+1}) and
+// sum e_i a_i = sum_pairs e_i (a_i - a_{i+1}); pairing first keeps the
+// rounding of the sums at the scale of the moments rather than of the
+// individual (larger, velocity-carrying) deviations.
+template <int Q, typename C>
+__device__ __forceinline__ void pair_moments(const C* a, C& m0, C& mx, C& my, C& mz) {
+  using S = Stencil<Q>;
+  C s = a[0], x = C(0), y = C(0), z = C(0);
+#pragma unroll
+  for (int i = 1; i < Q; i += 2) {
+    s += a[i] + a[i + 1];
+    const C dlt = a[i] - a[i + 1];
+    if (S::ex[i] != 0) x += S::ex[i] > 0 ? dlt : -dlt;
+    if (S::ey[i] != 0) y += S::ey[i] > 0 ? dlt : -dlt;
+    if (S::ez[i] != 0) z += S::ez[i] > 0 ? dlt : -dlt;
+  }
+  m0 = s; mx = x; my = y; mz = z;
+}
+
+template <int Q, typename C>
+__device__ __forceinline__ C pair_sum(const C* a) {
+  C s = a[0];
+#pragma unroll
+  for (int i = 1; i < Q; i += 2) s += a[i] + a[i + 1];
+  return s;
+}
+
+__device__ __forceinline__ float fma_c(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_c(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <typename C>
+__device__ __forceinline__ C dot_e(int ex, int ey, int ez, C vx, C vy, C vz) {
+  C eu = C(0);
+  if (ex != 0) eu += ex > 0 ? vx : -vx;
+  if (ey != 0) eu += ey > 0 ? vy : -vy;
+  if (ez != 0) eu += ez > 0 ? vz : -vz;
+  return eu;
+}
+
+template <typename C>
+struct NodeMacro {
+  C drho;       // rho - 1
+  C rho;
+  C jx, jy, jz; // sum e f
+  C dsig;       // sum g - 1
+  C rho_p;      // rho'
+  C s;          // -u'_z (d rho_b/dz)_LU
+  C Fz;         // -G rho'
+  C ux, uy, uz; // physical velocity, Eq. (7)
+  C vx, vy, vz; // velocity in the equilibria
+};
+
+template <int QF, int QG, int FORCE, typename C>
+__device__ __forceinline__ void node_macro(const C* f, const C* g, const PhysConsts& c,
+                                           NodeMacro<C>& m) {
+  C drho, jx, jy, jz;
+  pair_moments<QF>(f, drho, jx, jy, jz);
+  const C dsig = pair_sum<QG>(g);
+  const C rho = C(1) + drho;                  // Eq. (6), rho_0 = 1 plus deviation
+  const C inv_rho = C(1) / rho;
+  const C upz = jz * inv_rho;
+  const C s = -upz * (C)c.beta;               // Eqs. (12)-(13), bare u_z
+  const C rho_p = dsig + C(0.5) * s;          // Eqs. (16)-(17): sum g + S/2 - rho_0
+  const C Fz = -(C)c.G * rho_p;               // Eq. (18)
+  m.drho = drho; m.rho = rho; m.jx = jx; m.jy = jy; m.jz = jz;
+  m.dsig = dsig; m.rho_p = rho_p; m.s = s; m.Fz = Fz;
+  m.ux = jx * inv_rho;
+  m.uy = jy * inv_rho;
+  m.uz = upz + C(0.5) * Fz * inv_rho;         // Eq. (7)
+  m.vx = m.ux;
+  m.vy = m.uy;
+  if (FORCE == FORCE_GUO) m.vz = m.uz;
+  else m.vz = upz + (C)c.tau_f * Fz * inv_rho;  // Shan-Chen shift, Eq. (10) (tau F / rho)
+}
+
+// BGK collision of both lattices in place (Eqs. (5), (8), (9), (11), (14), (15)).
+//
+// The relaxation increment d_i = f_i^eq - f_i has, in exact arithmetic, zeroth
+// moment 0 and first moment rho u_eq - j (= F/2 for Guo, tau_f F for the shift);
+// the scalar increment has zeroth moment S/2.  Rounding breaks those identities
+// at the level of the velocity-carrying deviations, which at tau ~ 1/2 acts
+// as a spurious local mass / momentum source every step.  The increments are
+// therefore projected back onto their exact conserved moments
+// (d_i -= w_i (r_0 + e_i . r / c_s^2) with r the moment residual), which is the
+// identity in exact arithmetic.
+template <int QF, int QG, int FORCE, typename C>
+__device__ __forceinline__ void node_collide(C* f, C* g, const PhysConsts& c,
+                                             const NodeMacro<C>& m) {
+  using SF = Stencil<QF>;
+  using SG = Stencil<QG>;
+  const C vx = m.vx, vy = m.vy, vz = m.vz;
+  const C usq = vx * vx + vy * vy + vz * vz;
+  const C omega_f = (C)c.omega_f, omega_g = (C)c.omega_g;
+  // momentum lattice: df_eq = w [drho + rho (xi + xi^2/2 - u^2/(2 c^2))], xi = e.u / c^2
+  constexpr C icf = C(1.0 / SF::cs2);
+  const C base_f = m.drho - C(0.5) * icf * m.rho * usq;
+  auto feq = [&](int i) {
+    const C xi = icf * dot_e(SF::ex[i], SF::ey[i], SF::ez[i], vx, vy, vz);
+    return C(SF::w[i]) * (base_f + m.rho * xi * (C(1) + C(0.5) * xi));
+  };
+  // f[i] <- d_i = f_i^eq - f_i (so f_i = f_i^eq - d_i below)
+#pragma unroll
+  for (int i = 0; i < QF; ++i) f[i] = feq(i) - f[i];
+  C r0, rx, ry, rz;
+  pair_moments<QF>(f, r0, rx, ry, rz);
+  rz -= (FORCE == FORCE_GUO) ? C(0.5) * m.Fz : (C)c.tau_f * m.Fz;
+  const C guo_c = (FORCE == FORCE_GUO) ? (C(1) - C(0.5) * omega_f) * m.Fz : C(0);
+  // f*_i = f_i + omega (d_i - p_i) + G_i = f_i^eq + [(omega - 1) d_i - omega p_i + G_i],
+  // p_i = w_i (r_0 + e_i . r / c^2) the projection of the moment residual and G_i
+  // the Guo term.  The bracket is formed with fused multiply-adds so that the
+  // small terms (p_i, G_i ~ 1e-12) shift its single rounding instead of
+  // deciding ties of the final sum: ties broken by a term whose sign follows
+  // e_i . F would bias the node mass a little every step.
+#pragma unroll
+  for (int i = 0; i < QF; ++i) {
+    const C p = C(SF::w[i]) * (r0 + icf * dot_e(SF::ex[i], SF::ey[i], SF::ez[i], rx, ry, rz));
+    C small = -omega_f * p;
+    if (FORCE == FORCE_GUO) {
+      // Guo term with F = (0, 0, Fz): (1 - omega/2) w [(e_z - u_z) / c^2 + (e.u) e_z / c^4] Fz
+      const C eu = dot_e(SF::ex[i], SF::ey[i], SF::ez[i], vx, vy, vz);
+      C br = -icf * m.uz;
+      if (SF::ez[i] != 0) br += SF::ez[i] > 0 ? icf * (C(1) + icf * eu) : -icf * (C(1) + icf * eu);
+      small = fma_c(-omega_f, p, C(SF::w[i]) * guo_c * br);
+    }
+    f[i] = feq(i) + fma_c(omega_f - C(1), f[i], small);
+  }
+  // scalar lattice: dg_eq = w [rho' + (1 + rho') (xi + xi^2/2 - u^2/(2 c^2))]
+  constexpr C icg = C(1.0 / SG::cs2);
+  const C conc = C(1) + m.rho_p;
+  const C base_g = -C(0.5) * icg * usq;
+  auto geq = [&](int j) {
+    const C xi = icg * dot_e(SG::ex[j], SG::ey[j], SG::ez[j], vx, vy, vz);
+    return C(SG::w[j]) * (m.rho_p + conc * (base_g + xi * (C(1) + C(0.5) * xi)));
+  };
+#pragma unroll
+  for (int j = 0; j < QG; ++j) g[j] = geq(j) - g[j];
+  const C r0g = pair_sum<QG>(g) - C(0.5) * m.s;
+  const C src = (C(1) - C(0.5) * omega_g) * m.s - omega_g * r0g;
+#pragma unroll
+  for (int j = 0; j < QG; ++j) g[j] = geq(j) + fma_c(omega_g - C(1), g[j], C(SG::w[j]) * src);
+}
+
+// ---------------------------------------------------------------------------
+// block reductions (fixed order: deterministic)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Reduce NV per-thread values over the block and write them to out[0..NV).
+// Bit k of MAXMASK selects a maximum instead of a sum for entry k.  Every
+// thread of the block must call this (masked-out threads pass neutral values);
+// the block size must be a multiple of 64 and at most 1024.
+template <int NV, unsigned MAXMASK>
+__device__ __forceinline__ void block_reduce_store(const double* vals, double* __restrict__ out) {
+  __shared__ double lds[16][NV];
+  const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+  const int nthreads = blockDim.x * blockDim.y * blockDim.z;
+  const int lane = tid & 63, wid = tid >> 6, nw = nthreads >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const double r = ((MAXMASK >> k) & 1u) ? wave_max(vals[k]) : wave_sum(vals[k]);
+    if (lane == 0) lds[wid][k] = r;
+  }
+  __syncthreads();
+  if (tid == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double acc = lds[0][k];
+      for (int w = 1; w < nw; ++w)
+        acc = ((MAXMASK >> k) & 1u) ? fmax(acc, lds[w][k]) : acc + lds[w][k];
+      out[k] = acc;
+    }
+  }
+}
+
+}  // namespace stgv

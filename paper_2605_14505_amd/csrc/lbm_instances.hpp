@@ -1,0 +1,113 @@
+// Template instances of the node kernels for one storage type STGV_T and one
+// compute type STGV_C.  Included once per (storage, compute) pair by the
+// lbm_*.hip translation units; the layout kernels (init, canonicalise, load)
+// are instantiated by the FP32-compute unit of each storage type
+// (STGV_LAYOUT_KERNELS).
+#pragma once
+#include "lbm_kernels.hpp"
+#include "lbm_launch.hpp"
+
+namespace stgv {
+// Internal linkage: every (storage, compute) translation unit has its own
+// helpers, whose template arguments do not name the compute type.
+namespace {
+
+template <int QF, int QG, int FORCE, typename T, int MODE, int FLAGS>
+hipError_t go_step(const LaunchShape& sh, hipStream_t st, T* pop, T* dst, Geometry geo,
+                   PhysConsts c, float* fields, double* partials) {
+  hipLaunchKernelGGL((lbm_step_kernel<QF, QG, FORCE, T, STGV_C, MODE, FLAGS>), sh.grid, sh.block,
+                     0, st, pop, dst, geo, c, fields, partials);
+  return hipGetLastError();
+}
+
+template <int QF, int QG, typename T>
+hipError_t step_pair(int force, int mode, int flags, const LaunchShape& sh, hipStream_t st, T* pop,
+                     T* dst, Geometry geo, PhysConsts c, float* fields, double* partials) {
+  constexpr int STEP = K_COLLIDE;
+  constexpr int STEP_DIAG = K_COLLIDE | K_FIELDS | K_PARTIALS;
+  constexpr int SAMPLE = K_FIELDS | K_PARTIALS;
+  constexpr int FIELDS = K_FIELDS;
+#define STGV_GO(F, M, FL) return go_step<QF, QG, F, T, M, FL>(sh, st, pop, dst, geo, c, fields, partials)
+  if (flags == STEP || flags == STEP_DIAG) {
+    const bool d = flags == STEP_DIAG;
+    if (force == FORCE_GUO) {
+      if (mode == MODE_EVEN) { if (d) STGV_GO(FORCE_GUO, MODE_EVEN, STEP_DIAG); STGV_GO(FORCE_GUO, MODE_EVEN, STEP); }
+      if (mode == MODE_ODD) { if (d) STGV_GO(FORCE_GUO, MODE_ODD, STEP_DIAG); STGV_GO(FORCE_GUO, MODE_ODD, STEP); }
+      if (mode == MODE_AB) { if (d) STGV_GO(FORCE_GUO, MODE_AB, STEP_DIAG); STGV_GO(FORCE_GUO, MODE_AB, STEP); }
+    } else if (force == FORCE_SHIFT) {
+      if (mode == MODE_EVEN) { if (d) STGV_GO(FORCE_SHIFT, MODE_EVEN, STEP_DIAG); STGV_GO(FORCE_SHIFT, MODE_EVEN, STEP); }
+      if (mode == MODE_ODD) { if (d) STGV_GO(FORCE_SHIFT, MODE_ODD, STEP_DIAG); STGV_GO(FORCE_SHIFT, MODE_ODD, STEP); }
+      if (mode == MODE_AB) { if (d) STGV_GO(FORCE_SHIFT, MODE_AB, STEP_DIAG); STGV_GO(FORCE_SHIFT, MODE_AB, STEP); }
+    }
+    return hipErrorInvalidValue;
+  }
+  // Moment-only passes read the natural layout (MODE_EVEN, also the AB lattice)
+  // or the odd AA layout; the physical velocity does not depend on the forcing.
+  const int gm = (mode == MODE_ODD) ? MODE_ODD : MODE_EVEN;
+  if (flags == SAMPLE) {
+    if (gm == MODE_EVEN) STGV_GO(FORCE_GUO, MODE_EVEN, SAMPLE);
+    STGV_GO(FORCE_GUO, MODE_ODD, SAMPLE);
+  }
+  if (flags == FIELDS) {
+    if (gm == MODE_EVEN) STGV_GO(FORCE_GUO, MODE_EVEN, FIELDS);
+    STGV_GO(FORCE_GUO, MODE_ODD, FIELDS);
+  }
+#undef STGV_GO
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+template <>
+hipError_t launch_step<STGV_T, STGV_C>(int qf, int qg, int force, int mode, int flags,
+                               const LaunchShape& sh, hipStream_t st, STGV_T* pop, STGV_T* dst,
+                               Geometry geo, PhysConsts c, float* fields, double* partials) {
+  if (qf == 27 && qg == 19)
+    return step_pair<27, 19, STGV_T>(force, mode, flags, sh, st, pop, dst, geo, c, fields, partials);
+  if (qf == 27 && qg == 7)
+    return step_pair<27, 7, STGV_T>(force, mode, flags, sh, st, pop, dst, geo, c, fields, partials);
+  if (qf == 19 && qg == 7)
+    return step_pair<19, 7, STGV_T>(force, mode, flags, sh, st, pop, dst, geo, c, fields, partials);
+  return hipErrorInvalidValue;
+}
+
+#ifdef STGV_LAYOUT_KERNELS
+template <>
+hipError_t launch_init<STGV_T>(int qf, int qg, const LaunchShape& sh, hipStream_t st, STGV_T* pop,
+                               Geometry geo, double u0, double noise_amp, uint64_t seed) {
+#define STGV_INIT(A, B) \
+  if (qf == A && qg == B) { \
+    hipLaunchKernelGGL((lbm_init_tgv_kernel<A, B, STGV_T>), sh.grid, sh.block, 0, st, pop, geo, u0, noise_amp, seed); \
+    return hipGetLastError(); }
+  STGV_INIT(27, 19) STGV_INIT(27, 7) STGV_INIT(19, 7)
+#undef STGV_INIT
+  return hipErrorInvalidValue;
+}
+
+template <>
+hipError_t launch_canon<STGV_T>(int qf, int qg, int mode, const LaunchShape& sh, hipStream_t st,
+                                const STGV_T* pop, Geometry geo, float* out) {
+#define STGV_CANON(A, B) \
+  if (qf == A && qg == B) { \
+    if (mode == MODE_ODD) hipLaunchKernelGGL((lbm_canon_kernel<A, B, STGV_T, MODE_ODD>), sh.grid, sh.block, 0, st, pop, geo, out); \
+    else hipLaunchKernelGGL((lbm_canon_kernel<A, B, STGV_T, MODE_EVEN>), sh.grid, sh.block, 0, st, pop, geo, out); \
+    return hipGetLastError(); }
+  STGV_CANON(27, 19) STGV_CANON(27, 7) STGV_CANON(19, 7)
+#undef STGV_CANON
+  return hipErrorInvalidValue;
+}
+
+template <>
+hipError_t launch_load<STGV_T>(int qf, int qg, const LaunchShape& sh, hipStream_t st, STGV_T* pop,
+                               Geometry geo, const float* in) {
+#define STGV_LOAD(A, B) \
+  if (qf == A && qg == B) { \
+    hipLaunchKernelGGL((lbm_load_kernel<A, B, STGV_T>), sh.grid, sh.block, 0, st, pop, geo, in); \
+    return hipGetLastError(); }
+  STGV_LOAD(27, 19) STGV_LOAD(27, 7) STGV_LOAD(19, 7)
+#undef STGV_LOAD
+  return hipErrorInvalidValue;
+}
+#endif  // STGV_LAYOUT_KERNELS
+
+}  // namespace stgv

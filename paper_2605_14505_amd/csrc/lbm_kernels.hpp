@@ -1,0 +1,157 @@
+// Kernels of the DDF lattice Boltzmann step and its diagnostics (gfx950).
+#pragma once
+#include "lbm_device.hpp"
+
+namespace stgv {
+
+// ---------------------------------------------------------------------------
+// Fused stream-collide-force step (optionally with the diagnostic moments)
+//
+// Block (bx, by) threads over x and y; grid (ceil(n/bx), ceil(n/by), n).
+// `pop` is the population array (AA) or the source lattice (AB); `dst` is the
+// AB destination and equals `pop` otherwise.
+// ---------------------------------------------------------------------------
+template <int QF, int QG, int FORCE, typename T, typename C, int MODE, int FLAGS>
+__global__ __launch_bounds__(256) void lbm_step_kernel(T* pop, T* dst, Geometry geo,
+                                                       PhysConsts c, float* __restrict__ fields,
+                                                       double* __restrict__ partials) {
+  const int n = geo.n;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  const bool active = (x < n) && (y < n);
+  constexpr bool kPart = (FLAGS & K_PARTIALS) != 0;
+  if (!kPart && !active) return;
+
+  double acc[NPART];
+#pragma unroll
+  for (int k = 0; k < NPART; ++k) acc[k] = 0.0;
+
+  if (active) {
+    const NodeIndex ix = make_index(x, y, z, n);
+    C f[QF], g[QG];
+    gather<QF, T, MODE>(f, pop, 0, ix, geo.stride);
+    gather<QG, T, MODE>(g, pop, QF, ix, geo.stride);
+    NodeMacro<C> m;
+    node_macro<QF, QG, FORCE>(f, g, c, m);
+    if (FLAGS & K_FIELDS) {
+      const int64_t n3 = (int64_t)n * n * n;
+      fields[ix.base] = (float)m.drho;
+      fields[n3 + ix.base] = (float)m.ux;
+      fields[2 * n3 + ix.base] = (float)m.uy;
+      fields[3 * n3 + ix.base] = (float)m.uz;
+      fields[4 * n3 + ix.base] = (float)m.rho_p;
+    }
+    if (kPart) {
+      const C u2 = m.ux * m.ux + m.uy * m.uy + m.uz * m.uz;
+      const C ep = (C)c.g_over_n * m.rho_p;
+      acc[P_EK] = 0.5 * (double)u2;
+      acc[P_EP] = 0.5 * (double)(ep * ep);
+      acc[P_DRHO] = (double)m.drho;
+      acc[P_DSIG] = (double)m.dsig;
+      acc[P_MX] = (double)m.jx;
+      acc[P_MY] = (double)m.jy;
+      acc[P_MZ] = (double)(m.jz + C(0.5) * m.Fz);
+      acc[P_UMAX2] = (double)u2;
+      acc[P_NONFINITE] = (isfinite(m.rho) && isfinite(u2) && isfinite(m.rho_p)) ? 0.0 : 1.0;
+    }
+    if (FLAGS & K_COLLIDE) {
+      node_collide<QF, QG, FORCE>(f, g, c, m);
+      scatter<QF, T, MODE>(f, dst, 0, ix, geo.stride);
+      scatter<QG, T, MODE>(g, dst, QF, ix, geo.stride);
+    }
+  }
+  if (kPart) {
+    const int64_t blk = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
+    block_reduce_store<NPART, (1u << P_UMAX2)>(acc, partials + blk * NPART);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Taylor-Green initial state (Eqs. (20)-(21)) in natural order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  // one output of SplitMix64 (Steele, Lea & Flood 2014) from state x
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+template <int QF, int QG, typename T>
+__global__ __launch_bounds__(256) void lbm_init_tgv_kernel(T* pop, Geometry geo, double u0,
+                                                           double noise_amp, uint64_t seed) {
+  using SF = Stencil<QF>;
+  using SG = Stencil<QG>;
+  const int n = geo.n;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= n || y >= n) return;
+  const int64_t node = (int64_t)x + (int64_t)n * (y + (int64_t)n * z);
+  const double h = 2.0 * M_PI / n;
+  const double X = h * x, Y = h * y, Z = h * z;
+  const double vx = u0 * sin(X) * cos(Y) * cos(Z);
+  const double vy = -u0 * cos(X) * sin(Y) * cos(Z);
+  const double vz = 0.0;
+  const double p0 = u0 * u0 / 16.0 * (cos(2.0 * X) + cos(2.0 * Y)) * (cos(2.0 * Z) + 2.0);
+  const double drho = p0 / SF::cs2;
+  const double rho = 1.0 + drho;
+  const uint64_t ctr = (seed << 40) + (uint64_t)node;
+  const double xi = (double)(splitmix64(ctr) >> 11) * 0x1.0p-53;
+  const double rho_p = noise_amp * (2.0 * xi - 1.0);
+  const double usq = vx * vx + vy * vy + vz * vz;
+#pragma unroll
+  for (int i = 0; i < QF; ++i) {
+    const double eu = SF::ex[i] * vx + SF::ey[i] * vy + SF::ez[i] * vz;
+    const double d = SF::w[i] * (drho + rho * (eu / SF::cs2 + eu * eu / (2.0 * SF::cs2 * SF::cs2)
+                                               - usq / (2.0 * SF::cs2)));
+    store_as(pop + (int64_t)i * geo.stride + node, (float)d);
+  }
+#pragma unroll
+  for (int j = 0; j < QG; ++j) {
+    const double eu = SG::ex[j] * vx + SG::ey[j] * vy + SG::ez[j] * vz;
+    const double poly = eu / SG::cs2 + eu * eu / (2.0 * SG::cs2 * SG::cs2) - usq / (2.0 * SG::cs2);
+    const double d = SG::w[j] * (rho_p + (1.0 + rho_p) * poly);
+    store_as(pop + (int64_t)(QF + j) * geo.stride + node, (float)d);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Layout conversion: current layout -> natural FP32 deviations, and back.
+// ---------------------------------------------------------------------------
+template <int QF, int QG, typename T, int MODE>
+__global__ __launch_bounds__(256) void lbm_canon_kernel(const T* pop, Geometry geo,
+                                                        float* __restrict__ out) {
+  const int n = geo.n;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= n || y >= n) return;
+  const NodeIndex ix = make_index(x, y, z, n);
+  const int64_t n3 = (int64_t)n * n * n;
+  float f[QF], g[QG];
+  gather<QF, T, MODE>(f, pop, 0, ix, geo.stride);
+  gather<QG, T, MODE>(g, pop, QF, ix, geo.stride);
+#pragma unroll
+  for (int i = 0; i < QF; ++i) out[i * n3 + ix.base] = f[i];
+#pragma unroll
+  for (int j = 0; j < QG; ++j) out[(QF + j) * n3 + ix.base] = g[j];
+}
+
+template <int QF, int QG, typename T>
+__global__ __launch_bounds__(256) void lbm_load_kernel(T* pop, Geometry geo,
+                                                       const float* __restrict__ in) {
+  const int n = geo.n;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= n || y >= n) return;
+  const int64_t n3 = (int64_t)n * n * n;
+  const int64_t node = (int64_t)x + (int64_t)n * (y + (int64_t)n * z);
+#pragma unroll
+  for (int i = 0; i < QF + QG; ++i)
+    store_as(pop + (int64_t)i * geo.stride + node, in[i * n3 + node]);
+}
+
+}  // namespace stgv

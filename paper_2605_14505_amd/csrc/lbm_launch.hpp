@@ -1,0 +1,51 @@
+// Host-side launchers: map run-time choices (stencil pair, forcing, layout mode,
+// kernel flags) onto the kernel template instances of one storage type.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "lbm_device.hpp"
+
+namespace stgv {
+
+struct LaunchShape {
+  dim3 grid, block;
+};
+
+// Launch shape of the node kernels: block (bx, by) over x and y, grid over
+// (x, y, z).  Blocks are 256 threads except when a row is shorter than a
+// wavefront; every block is a whole number of 64-wide wavefronts.
+inline LaunchShape node_shape(int n) {
+  int bx, by;
+  if (n <= 64 && 64 % n == 0) {
+    bx = n;
+    by = 256 / n;
+  } else {
+    bx = ((n + 63) / 64) * 64;
+    if (bx > 256) bx = 256;
+    by = 256 / bx;
+  }
+  LaunchShape s;
+  s.block = dim3(bx, by, 1);
+  s.grid = dim3((n + bx - 1) / bx, (n + by - 1) / by, n);
+  return s;
+}
+
+// Every function returns the launch error (hipSuccess when queued).
+template <typename T, typename C>
+hipError_t launch_step(int qf, int qg, int force, int mode, int flags, const LaunchShape& sh,
+                       hipStream_t st, T* pop, T* dst, Geometry geo, PhysConsts c,
+                       float* fields, double* partials);
+
+template <typename T>
+hipError_t launch_init(int qf, int qg, const LaunchShape& sh, hipStream_t st, T* pop, Geometry geo,
+                       double u0, double noise_amp, uint64_t seed);
+
+template <typename T>
+hipError_t launch_canon(int qf, int qg, int mode, const LaunchShape& sh, hipStream_t st,
+                        const T* pop, Geometry geo, float* out);
+
+template <typename T>
+hipError_t launch_load(int qf, int qg, const LaunchShape& sh, hipStream_t st, T* pop,
+                       Geometry geo, const float* in);
+
+}  // namespace stgv

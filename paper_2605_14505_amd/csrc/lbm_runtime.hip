@@ -1,0 +1,661 @@
+// Host runtime and C ABI of the stratified-TGV DDF lattice Boltzmann step
+// (declared in include/stgv.h), plus the diagnostic reduction kernels and the
+// streaming-bandwidth probe.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "../../include/stgv.h"
+#include "lbm_device.hpp"
+#include "lbm_launch.hpp"
+
+namespace stgv {
+
+// ---------------------------------------------------------------------------
+// Dissipation stencil: eps_k needs |curl u|^2 and eps_p needs |grad rho'|^2 by
+// second-order central differences (periodic).  A 64 x 4 tile of x-y columns
+// marches up a chunk of z; each z-plane of the tile plus a one-node halo is
+// staged in LDS for the in-plane derivatives, and the z-neighbours of the own
+// column stay in registers.
+// ---------------------------------------------------------------------------
+constexpr int FD_TX = 64, FD_TY = 4, FD_ZC = 32;
+
+__global__ __launch_bounds__(256) void lbm_fd_kernel(const float* __restrict__ fields, int n,
+                                                     double* __restrict__ partials) {
+  __shared__ float plane[4][FD_TY + 2][FD_TX + 2];     // u_x, u_y, u_z, rho'
+  const int64_t n2 = (int64_t)n * n, n3 = n2 * n;
+  const float* ux = fields + n3;
+  const float* uy = fields + 2 * n3;
+  const float* uz = fields + 3 * n3;
+  const float* rp = fields + 4 * n3;
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int tid = tx + FD_TX * ty;
+  const int x0 = blockIdx.x * FD_TX, y0 = blockIdx.y * FD_TY;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool active = (x < n) && (y < n);
+  const int z0 = blockIdx.z * FD_ZC;
+  const int z1 = min(z0 + FD_ZC, n);
+  const int64_t col = (int64_t)(active ? x : 0) + (int64_t)n * (active ? y : 0);
+
+  // own column at z - 1 and z
+  auto zwrap = [n](int z) { return z < 0 ? z + n : (z >= n ? z - n : z); };
+  float cx_m = ux[col + n2 * zwrap(z0 - 1)], cx_0 = ux[col + n2 * z0];
+  float cy_m = uy[col + n2 * zwrap(z0 - 1)], cy_0 = uy[col + n2 * z0];
+  float cr_m = rp[col + n2 * zwrap(z0 - 1)], cr_0 = rp[col + n2 * z0];
+  double curl2 = 0.0, grad2 = 0.0;
+
+  for (int z = z0; z < z1; ++z) {
+    const int64_t zoff = n2 * z;
+    __syncthreads();
+    for (int c = tid; c < (FD_TY + 2) * (FD_TX + 2); c += FD_TX * FD_TY) {
+      const int ly = c / (FD_TX + 2), lx = c % (FD_TX + 2);
+      const int gx = (x0 + lx - 1 + n) % n, gy = (y0 + ly - 1 + n) % n;
+      const int64_t a = zoff + gx + (int64_t)n * gy;
+      plane[0][ly][lx] = ux[a];
+      plane[1][ly][lx] = uy[a];
+      plane[2][ly][lx] = uz[a];
+      plane[3][ly][lx] = rp[a];
+    }
+    __syncthreads();
+    const int64_t zp = n2 * zwrap(z + 1);
+    const float cx_p = ux[col + zp], cy_p = uy[col + zp], cr_p = rp[col + zp];
+    if (active) {
+      const int lx = tx + 1, ly = ty + 1;
+      const float duz_dx = 0.5f * (plane[2][ly][lx + 1] - plane[2][ly][lx - 1]);
+      const float duz_dy = 0.5f * (plane[2][ly + 1][lx] - plane[2][ly - 1][lx]);
+      const float duy_dx = 0.5f * (plane[1][ly][lx + 1] - plane[1][ly][lx - 1]);
+      const float dux_dy = 0.5f * (plane[0][ly + 1][lx] - plane[0][ly - 1][lx]);
+      const float dux_dz = 0.5f * (cx_p - cx_m);
+      const float duy_dz = 0.5f * (cy_p - cy_m);
+      const float wx = duz_dy - duy_dz, wy = dux_dz - duz_dx, wz = duy_dx - dux_dy;
+      curl2 += (double)(wx * wx + wy * wy + wz * wz);
+      const float gx = 0.5f * (plane[3][ly][lx + 1] - plane[3][ly][lx - 1]);
+      const float gy = 0.5f * (plane[3][ly + 1][lx] - plane[3][ly - 1][lx]);
+      const float gz = 0.5f * (cr_p - cr_m);
+      grad2 += (double)(gx * gx + gy * gy + gz * gz);
+    }
+    cx_m = cx_0; cx_0 = cx_p;
+    cy_m = cy_0; cy_0 = cy_p;
+    cr_m = cr_0; cr_0 = cr_p;
+  }
+  const double v[NFD] = {curl2, grad2};
+  const int64_t blk = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
+  block_reduce_store<NFD, 0u>(v, partials + blk * NFD);
+}
+
+// ---------------------------------------------------------------------------
+// Final fixed-order FP64 reduction of the per-block partials into one record.
+// One block of 256 threads.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void lbm_final_kernel(const double* __restrict__ sp, int64_t nsp,
+                                                        const double* __restrict__ fp, int64_t nfp,
+                                                        double* __restrict__ rec, int64_t step) {
+  constexpr int NV = NPART + NFD;
+  double v[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = 0.0;
+  for (int64_t b = threadIdx.x; b < nsp; b += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < NPART; ++k)
+      v[k] = (k == P_UMAX2) ? fmax(v[k], sp[b * NPART + k]) : v[k] + sp[b * NPART + k];
+  }
+  for (int64_t b = threadIdx.x; b < nfp; b += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < NFD; ++k) v[NPART + k] += fp[b * NFD + k];
+  }
+  __shared__ double out[NV];
+  block_reduce_store<NV, (1u << P_UMAX2)>(v, out);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r[NREC] = {0};
+    r[R_STEP] = (double)step;
+    r[R_EK] = out[P_EK];
+    r[R_EP] = out[P_EP];
+    r[R_CURL2] = out[NPART + FD_CURL2];
+    r[R_GRAD2] = out[NPART + FD_GRAD2];
+    r[R_DRHO] = out[P_DRHO];
+    r[R_DSIG] = out[P_DSIG];
+    r[R_MX] = out[P_MX];
+    r[R_MY] = out[P_MY];
+    r[R_MZ] = out[P_MZ];
+    r[R_UMAX2] = out[P_UMAX2];
+    r[R_NONFINITE] = out[P_NONFINITE];
+    for (int k = 0; k < NREC; ++k) rec[k] = r[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Streaming-bandwidth probe: the achievable HBM ceiling for the step's pattern
+// of long unit-stride streams.  Grid-stride loops over 16-byte vectors.
+// ---------------------------------------------------------------------------
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void bw_copy_kernel(v4f* __restrict__ dst,
+                                                      const v4f* __restrict__ src, int64_t nv) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nv;
+       i += (int64_t)gridDim.x * blockDim.x)
+    __builtin_nontemporal_store(src[i], dst + i);
+}
+__global__ __launch_bounds__(256) void bw_read_kernel(float* __restrict__ dst,
+                                                      const v4f* __restrict__ src, int64_t nv) {
+  float acc = 0.f;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nv;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const v4f v = src[i];
+    acc += v.x + v.y + v.z + v.w;
+  }
+  __shared__ float red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) dst[blockIdx.x] = red[0];
+}
+__global__ __launch_bounds__(256) void bw_write_kernel(v4f* __restrict__ dst, int64_t nv) {
+  const v4f v = {0.f, 0.f, 0.f, 0.f};
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nv;
+       i += (int64_t)gridDim.x * blockDim.x)
+    __builtin_nontemporal_store(v, dst + i);
+}
+
+}  // namespace stgv
+
+// ===========================================================================
+// Host side
+// ===========================================================================
+using namespace stgv;
+
+namespace {
+
+constexpr int kRingCap = 4096;
+constexpr size_t kAlign = 256;
+
+thread_local char g_err[512] = "";
+
+struct Derived {
+  double L, nu, D, tau_f, tau_g, nb, G, beta, cs2_f, cs2_g;
+};
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+void set_err(char* buf, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, 512, fmt, ap);
+  va_end(ap);
+}
+
+double lattice_cs2(int q) { return q == 7 ? 0.25 : 1.0 / 3.0; }
+
+bool valid_pair(int qf, int qg) {
+  return (qf == 27 && qg == 19) || (qf == 27 && qg == 7) || (qf == 19 && qg == 7);
+}
+
+// Parameter checks and the lattice-unit constants of Eqs. (8), (13), (14), (19)
+// with U = u0, L = n / (2 pi), rho_0 = 1 and G = (G/N) N.
+int derive(const lbm_params* p, Derived* d, char* err) {
+  if (!p) { set_err(err, "params is NULL"); return LBM_EINVAL; }
+  if (p->n < 4 || p->n > 1024) { set_err(err, "n = %d outside [4, 1024]", p->n); return LBM_EINVAL; }
+  if (!valid_pair(p->q_f, p->q_g)) {
+    set_err(err, "stencil pair D3Q%d x D3Q%d not supported (27x19, 27x7, 19x7)", p->q_f, p->q_g);
+    return LBM_EINVAL;
+  }
+  if (p->forcing != LBM_FORCE_GUO && p->forcing != LBM_FORCE_SHIFT) {
+    set_err(err, "forcing = %d invalid", p->forcing); return LBM_EINVAL;
+  }
+  if (p->storage < LBM_FP32 || p->storage > LBM_BF16) {
+    set_err(err, "storage = %d invalid", p->storage); return LBM_EINVAL;
+  }
+  if (p->compute != LBM_COMPUTE_FP32 && p->compute != LBM_COMPUTE_FP64) {
+    set_err(err, "compute = %d invalid", p->compute); return LBM_EINVAL;
+  }
+  if (p->compute == LBM_COMPUTE_FP64 && p->storage != LBM_FP32) {
+    set_err(err, "FP64 arithmetic is available with FP32 storage only"); return LBM_EINVAL;
+  }
+  if (p->reserved != 0) { set_err(err, "reserved field must be 0"); return LBM_EINVAL; }
+  if (p->layout != LBM_LAYOUT_AA && p->layout != LBM_LAYOUT_AB) {
+    set_err(err, "layout = %d invalid", p->layout); return LBM_EINVAL;
+  }
+  if (p->diag_every < 0) { set_err(err, "diag_every = %d < 0", p->diag_every); return LBM_EINVAL; }
+  if (!(std::isfinite(p->u0) && p->u0 > 0.0 && p->u0 < 0.3)) {
+    set_err(err, "u0 = %g outside (0, 0.3)", p->u0); return LBM_EINVAL;
+  }
+  if (!(std::isfinite(p->re) && p->re > 0.0)) { set_err(err, "re = %g must be > 0", p->re); return LBM_EINVAL; }
+  if (!(std::isfinite(p->sc) && p->sc > 0.0)) { set_err(err, "sc = %g must be > 0", p->sc); return LBM_EINVAL; }
+  if (!(p->fr > 0.0) || std::isnan(p->fr)) { set_err(err, "fr = %g must be > 0 (inf allowed)", p->fr); return LBM_EINVAL; }
+  if (!(std::isfinite(p->g_over_n) && p->g_over_n > 0.0)) {
+    set_err(err, "g_over_n = %g must be finite and > 0", p->g_over_n); return LBM_EINVAL;
+  }
+  if (!(std::isfinite(p->noise_amp) && p->noise_amp >= 0.0)) {
+    set_err(err, "noise_amp = %g must be finite and >= 0", p->noise_amp); return LBM_EINVAL;
+  }
+  Derived o;
+  o.cs2_f = lattice_cs2(p->q_f);
+  o.cs2_g = lattice_cs2(p->q_g);
+  o.L = p->n / (2.0 * M_PI);
+  o.nu = p->u0 * o.L / p->re;
+  o.D = o.nu / p->sc;
+  o.tau_f = o.nu / o.cs2_f + 0.5;
+  o.tau_g = o.D / o.cs2_g + 0.5;
+  o.nb = std::isinf(p->fr) ? 0.0 : p->u0 / (p->fr * o.L);
+  o.G = p->g_over_n * o.nb;
+  o.beta = o.G != 0.0 ? -o.nb * o.nb / o.G : 0.0;
+  if (!(o.tau_f > 0.5) || !(o.tau_g > 0.5) || !std::isfinite(o.tau_f) || !std::isfinite(o.tau_g)) {
+    set_err(err, "relaxation times tau_f = %.17g, tau_g = %.17g must exceed 1/2", o.tau_f, o.tau_g);
+    return LBM_EINVAL;
+  }
+  if (d) *d = o;
+  return LBM_OK;
+}
+
+struct Sizes {
+  int64_t n3, stride;
+  size_t elem, pop_bytes;
+  size_t off_fields, off_sp, off_fp, off_ring, work_bytes;
+  int64_t nsp, nfp;
+};
+
+size_t elem_size(int storage) { return storage == LBM_FP32 ? 4 : 2; }
+
+Sizes sizes_of(const lbm_params* p) {
+  Sizes s;
+  const int64_t n = p->n;
+  s.n3 = n * n * n;
+  s.elem = elem_size(p->storage);
+  // Arrays start on 256-byte boundaries; the default pad of 1 KiB (plus the
+  // alignment) keeps the Q_f + Q_g streams off a power-of-two stride.
+  const int64_t per_line = (int64_t)(kAlign / s.elem);
+  const int64_t pad = p->pad >= 0 ? p->pad : (int64_t)(1024 / s.elem);
+  s.stride = ((s.n3 + pad + per_line - 1) / per_line) * per_line;
+  const int64_t arrays = (int64_t)(p->q_f + p->q_g) * (p->layout == LBM_LAYOUT_AB ? 2 : 1);
+  s.pop_bytes = (size_t)(arrays * s.stride) * s.elem;
+  const LaunchShape sh = node_shape(p->n);
+  s.nsp = (int64_t)sh.grid.x * sh.grid.y * sh.grid.z;
+  s.nfp = (int64_t)((p->n + FD_TX - 1) / FD_TX) * ((p->n + FD_TY - 1) / FD_TY) * ((p->n + FD_ZC - 1) / FD_ZC);
+  size_t off = 0;
+  s.off_fields = off; off = align_up(off + (size_t)(5 * s.n3) * sizeof(float), kAlign);
+  s.off_sp = off;     off = align_up(off + (size_t)(s.nsp * NPART) * sizeof(double), kAlign);
+  s.off_fp = off;     off = align_up(off + (size_t)(s.nfp * NFD) * sizeof(double), kAlign);
+  s.off_ring = off;   off = align_up(off + (size_t)kRingCap * NREC * sizeof(double), kAlign);
+  s.work_bytes = off;
+  return s;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_params p;
+  Derived d;
+  Sizes sz;
+  LaunchShape sh;
+  PhysConsts c;
+  Geometry geo;
+  char* pop;           // AA array, or the first AB lattice
+  char* pop_b;         // second AB lattice (nullptr for AA)
+  char* work;
+  hipStream_t stream;
+  int64_t step;
+  int odd;             // AA: the array holds the odd-step layout; AB: pop_b is current
+  int64_t ring_head;   // records queued
+  int64_t ring_tail;   // records drained
+  char err[512];
+};
+
+namespace {
+
+int hip_fail(lbm_ctx* ctx, hipError_t e, const char* what) {
+  char* buf = ctx ? ctx->err : g_err;
+  set_err(buf, "%s: %s", what, hipGetErrorString(e));
+  return LBM_EHIP;
+}
+
+template <typename F>
+hipError_t by_storage(int storage, F&& f) {
+  switch (storage) {
+    case LBM_FP32: return f((float*)nullptr);
+    case LBM_FP16: return f((_Float16*)nullptr);
+    default: return f((bf16_t*)nullptr);
+  }
+}
+
+// Node-kernel launch for the context's storage and compute types.
+hipError_t launch_node(lbm_ctx* c, int mode, int flags, char* src, char* dst, float* fields,
+                       double* partials);
+
+float* fields_buf(lbm_ctx* c) { return (float*)(c->work + c->sz.off_fields); }
+double* sp_buf(lbm_ctx* c) { return (double*)(c->work + c->sz.off_sp); }
+double* fp_buf(lbm_ctx* c) { return (double*)(c->work + c->sz.off_fp); }
+double* ring_buf(lbm_ctx* c) { return (double*)(c->work + c->sz.off_ring); }
+
+// Layout of the current state for the gather of a moment-only pass.
+int current_mode(const lbm_ctx* c) {
+  if (c->p.layout == LBM_LAYOUT_AB) return MODE_EVEN;
+  return c->odd ? MODE_ODD : MODE_EVEN;
+}
+char* current_array(const lbm_ctx* c) {
+  return (c->p.layout == LBM_LAYOUT_AB && c->odd) ? c->pop_b : c->pop;
+}
+
+// Queue the dissipation stencil and the final reduction into the next ring slot.
+hipError_t queue_record(lbm_ctx* c, int64_t step) {
+  const dim3 fblock(FD_TX, FD_TY, 1);
+  const dim3 fgrid((c->p.n + FD_TX - 1) / FD_TX, (c->p.n + FD_TY - 1) / FD_TY,
+                   (c->p.n + FD_ZC - 1) / FD_ZC);
+  hipLaunchKernelGGL(lbm_fd_kernel, fgrid, fblock, 0, c->stream, fields_buf(c), c->p.n, fp_buf(c));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  double* slot = ring_buf(c) + (c->ring_head % kRingCap) * NREC;
+  hipLaunchKernelGGL(lbm_final_kernel, dim3(1), dim3(256), 0, c->stream, sp_buf(c), c->sz.nsp,
+                     fp_buf(c), c->sz.nfp, slot, step);
+  e = hipGetLastError();
+  if (e == hipSuccess) c->ring_head++;
+  return e;
+}
+
+}  // namespace
+
+namespace {
+hipError_t launch_node(lbm_ctx* c, int mode, int flags, char* src, char* dst, float* fields,
+                       double* partials) {
+  const int qf = c->p.q_f, qg = c->p.q_g, fo = c->p.forcing;
+  switch (c->p.storage) {
+    case LBM_FP32:
+      if (c->p.compute == LBM_COMPUTE_FP64)
+        return launch_step<float, double>(qf, qg, fo, mode, flags, c->sh, c->stream, (float*)src,
+                                          (float*)dst, c->geo, c->c, fields, partials);
+      return launch_step<float, float>(qf, qg, fo, mode, flags, c->sh, c->stream, (float*)src,
+                                       (float*)dst, c->geo, c->c, fields, partials);
+    case LBM_FP16:
+      return launch_step<_Float16, float>(qf, qg, fo, mode, flags, c->sh, c->stream, (_Float16*)src,
+                                          (_Float16*)dst, c->geo, c->c, fields, partials);
+    default:
+      return launch_step<bf16_t, float>(qf, qg, fo, mode, flags, c->sh, c->stream, (bf16_t*)src,
+                                        (bf16_t*)dst, c->geo, c->c, fields, partials);
+  }
+}
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int lbm_query_sizes(const lbm_params* p, size_t* pop_bytes, size_t* work_bytes) {
+  const int rc = derive(p, nullptr, g_err);
+  if (rc != LBM_OK) return rc;
+  const Sizes s = sizes_of(p);
+  if (pop_bytes) *pop_bytes = s.pop_bytes;
+  if (work_bytes) *work_bytes = s.work_bytes;
+  return LBM_OK;
+}
+
+int lbm_derived(const lbm_params* p, double* out) {
+  Derived d;
+  const int rc = derive(p, &d, g_err);
+  if (rc != LBM_OK) return rc;
+  if (!out) { set_err(g_err, "out is NULL"); return LBM_EINVAL; }
+  const double v[8] = {d.L, d.nu, d.D, d.tau_f, d.tau_g, d.nb, d.G, d.beta};
+  memcpy(out, v, sizeof(v));
+  return LBM_OK;
+}
+
+int lbm_init_tgv(const lbm_params* p, void* pop_dev, size_t pop_bytes, void* work_dev,
+                 size_t work_bytes, void* hip_stream, lbm_ctx** out) {
+  if (!out) { set_err(g_err, "out is NULL"); return LBM_EINVAL; }
+  *out = nullptr;
+  Derived d;
+  int rc = derive(p, &d, g_err);
+  if (rc != LBM_OK) return rc;
+  const Sizes s = sizes_of(p);
+  if (!pop_dev || !work_dev) { set_err(g_err, "device buffer is NULL"); return LBM_EINVAL; }
+  if (((uintptr_t)pop_dev % kAlign) || ((uintptr_t)work_dev % kAlign)) {
+    set_err(g_err, "device buffers must be %zu-byte aligned", kAlign); return LBM_EINVAL;
+  }
+  if (pop_bytes < s.pop_bytes) {
+    set_err(g_err, "population buffer has %zu bytes, needs %zu", pop_bytes, s.pop_bytes);
+    return LBM_ESIZE;
+  }
+  if (work_bytes < s.work_bytes) {
+    set_err(g_err, "work buffer has %zu bytes, needs %zu", work_bytes, s.work_bytes);
+    return LBM_ESIZE;
+  }
+  lbm_ctx* c = new (std::nothrow) lbm_ctx();
+  if (!c) { set_err(g_err, "out of host memory"); return LBM_EINVAL; }
+  c->p = *p;
+  c->d = d;
+  c->sz = s;
+  c->sh = node_shape(p->n);
+  c->c.omega_f = 1.0 / d.tau_f;
+  c->c.omega_g = 1.0 / d.tau_g;
+  c->c.tau_f = d.tau_f;
+  c->c.G = d.G;
+  c->c.beta = d.beta;
+  c->c.g_over_n = p->g_over_n;
+  c->geo.n = p->n;
+  c->geo.stride = s.stride;
+  c->pop = (char*)pop_dev;
+  c->pop_b = p->layout == LBM_LAYOUT_AB
+                 ? (char*)pop_dev + (size_t)(p->q_f + p->q_g) * s.stride * s.elem
+                 : nullptr;
+  c->work = (char*)work_dev;
+  c->stream = (hipStream_t)hip_stream;
+  c->step = 0;
+  c->odd = 0;
+  c->ring_head = c->ring_tail = 0;
+  c->err[0] = 0;
+  hipError_t e = by_storage(p->storage, [&](auto* tag) {
+    using T = std::remove_pointer_t<decltype(tag)>;
+    return launch_init<T>(p->q_f, p->q_g, c->sh, c->stream, (T*)c->pop, c->geo, p->u0,
+                          p->noise_amp, p->seed);
+  });
+  if (e != hipSuccess) {
+    hip_fail(nullptr, e, "init kernel");
+    delete c;
+    return LBM_EHIP;
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* c, int64_t nsteps) {
+  if (!c) { set_err(g_err, "ctx is NULL"); return LBM_EINVAL; }
+  if (nsteps < 0) { set_err(c->err, "n = %lld < 0", (long long)nsteps); return LBM_EINVAL; }
+  const int64_t k = c->p.diag_every;
+  if (k > 0 && nsteps > 0) {
+    // records in [step, step + n): multiples of k
+    const int64_t first = (c->step + k - 1) / k, last = (c->step + nsteps - 1) / k;
+    const int64_t count = last - first + 1;
+    if (c->ring_head - c->ring_tail + count > kRingCap) {
+      set_err(c->err, "diagnostics ring would overflow (%lld pending + %lld new > %d): drain it first",
+              (long long)(c->ring_head - c->ring_tail), (long long)count, kRingCap);
+      return LBM_ESTATE;
+    }
+  }
+  for (int64_t s = 0; s < nsteps; ++s) {
+    const bool diag = k > 0 && (c->step % k) == 0;
+    const int flags = diag ? (K_COLLIDE | K_FIELDS | K_PARTIALS) : K_COLLIDE;
+    int mode;
+    char *src, *dst;
+    if (c->p.layout == LBM_LAYOUT_AB) {
+      mode = MODE_AB;
+      src = c->odd ? c->pop_b : c->pop;
+      dst = c->odd ? c->pop : c->pop_b;
+    } else {
+      mode = c->odd ? MODE_ODD : MODE_EVEN;
+      src = dst = c->pop;
+    }
+    hipError_t e = launch_node(c, mode, flags, src, dst, fields_buf(c), sp_buf(c));
+    if (e != hipSuccess) return hip_fail(c, e, "step kernel");
+    if (diag) {
+      e = queue_record(c, c->step);
+      if (e != hipSuccess) return hip_fail(c, e, "diagnostic kernels");
+    }
+    c->step++;
+    c->odd ^= 1;
+  }
+  return LBM_OK;
+}
+
+int lbm_sample(lbm_ctx* c) {
+  if (!c) { set_err(g_err, "ctx is NULL"); return LBM_EINVAL; }
+  if (c->ring_head - c->ring_tail + 1 > kRingCap) {
+    set_err(c->err, "diagnostics ring full: drain it first");
+    return LBM_ESTATE;
+  }
+  const int mode = current_mode(c);
+  char* src = current_array(c);
+  hipError_t e = launch_node(c, mode, K_FIELDS | K_PARTIALS, src, src, fields_buf(c), sp_buf(c));
+  if (e != hipSuccess) return hip_fail(c, e, "moments kernel");
+  e = queue_record(c, c->step);
+  if (e != hipSuccess) return hip_fail(c, e, "diagnostic kernels");
+  return LBM_OK;
+}
+
+int lbm_diagnostics(lbm_ctx* c, lbm_diag* out, int32_t max, int32_t* n_out) {
+  if (!c) { set_err(g_err, "ctx is NULL"); return LBM_EINVAL; }
+  if (n_out) *n_out = 0;
+  if (max < 0 || (max > 0 && !out)) { set_err(c->err, "invalid output array"); return LBM_EINVAL; }
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+  const int64_t pending = c->ring_head - c->ring_tail;
+  const int64_t take = pending < max ? pending : max;
+  const double n3 = (double)c->sz.n3;
+  const double u0 = c->p.u0, L = c->d.L;
+  const double e_scale = 1.0 / (n3 * u0 * u0);
+  const double eps_scale = L / (n3 * u0 * u0 * u0);
+  const double cs = std::sqrt(c->d.cs2_f);
+  int rc = LBM_OK;
+  double rec[NREC];
+  for (int64_t r = 0; r < take; ++r) {
+    const int64_t slot = (c->ring_tail + r) % kRingCap;
+    e = hipMemcpy(rec, ring_buf(c) + slot * NREC, sizeof(rec), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMemcpy ring");
+    lbm_diag& o = out[r];
+    o.step = (int64_t)rec[R_STEP];
+    o.t = o.step * u0 / L;
+    o.ek = rec[R_EK] * e_scale;
+    o.ep = c->d.G != 0.0 ? rec[R_EP] * e_scale : 0.0;
+    o.eps_k = c->d.nu * rec[R_CURL2] * eps_scale;
+    o.eps_p = c->d.G != 0.0 ? c->d.D * c->p.g_over_n * c->p.g_over_n * rec[R_GRAD2] * eps_scale : 0.0;
+    o.mass = n3 + rec[R_DRHO];
+    o.scalar = n3 + rec[R_DSIG];
+    o.mom[0] = rec[R_MX];
+    o.mom[1] = rec[R_MY];
+    o.mom[2] = rec[R_MZ];
+    o.umax = std::sqrt(rec[R_UMAX2]);
+    o.nonfinite = (int64_t)rec[R_NONFINITE];
+    if (o.nonfinite > 0 || !(o.umax <= cs)) {
+      set_err(c->err, "unstable state at step %lld: %lld non-finite nodes, max|u| = %g",
+              (long long)o.step, (long long)o.nonfinite, o.umax);
+      rc = LBM_EUNSTABLE;
+    }
+  }
+  c->ring_tail += take;
+  if (n_out) *n_out = (int32_t)take;
+  return rc;
+}
+
+int lbm_read_fields(lbm_ctx* c, float* dev_out) {
+  if (!c) { set_err(g_err, "ctx is NULL"); return LBM_EINVAL; }
+  if (!dev_out) { set_err(c->err, "dev_out is NULL"); return LBM_EINVAL; }
+  const int mode = current_mode(c);
+  char* src = current_array(c);
+  hipError_t e = launch_node(c, mode, K_FIELDS, src, src, dev_out, nullptr);
+  if (e != hipSuccess) return hip_fail(c, e, "fields kernel");
+  e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+  return LBM_OK;
+}
+
+int lbm_read_populations(lbm_ctx* c, float* dev_out) {
+  if (!c) { set_err(g_err, "ctx is NULL"); return LBM_EINVAL; }
+  if (!dev_out) { set_err(c->err, "dev_out is NULL"); return LBM_EINVAL; }
+  const int mode = current_mode(c);
+  char* src = current_array(c);
+  hipError_t e = by_storage(c->p.storage, [&](auto* tag) {
+    using T = std::remove_pointer_t<decltype(tag)>;
+    return launch_canon<T>(c->p.q_f, c->p.q_g, mode, c->sh, c->stream, (const T*)src, c->geo, dev_out);
+  });
+  if (e != hipSuccess) return hip_fail(c, e, "canonicalise kernel");
+  e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+  return LBM_OK;
+}
+
+int lbm_load_populations(lbm_ctx* c, const float* dev_in, int64_t step) {
+  if (!c) { set_err(g_err, "ctx is NULL"); return LBM_EINVAL; }
+  if (!dev_in) { set_err(c->err, "dev_in is NULL"); return LBM_EINVAL; }
+  if (step < 0) { set_err(c->err, "step = %lld < 0", (long long)step); return LBM_EINVAL; }
+  hipError_t e = by_storage(c->p.storage, [&](auto* tag) {
+    using T = std::remove_pointer_t<decltype(tag)>;
+    return launch_load<T>(c->p.q_f, c->p.q_g, c->sh, c->stream, (T*)c->pop, c->geo, dev_in);
+  });
+  if (e != hipSuccess) return hip_fail(c, e, "load kernel");
+  e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+  c->odd = 0;
+  c->step = step;
+  return LBM_OK;
+}
+
+int lbm_stencil_info(int32_t q, int32_t* e, double* w, double* cs2) {
+  auto fill = [&](auto S) {
+    using St = decltype(S);
+    for (int i = 0; i < St::q; ++i) {
+      if (e) { e[3 * i] = St::ex[i]; e[3 * i + 1] = St::ey[i]; e[3 * i + 2] = St::ez[i]; }
+      if (w) w[i] = St::w[i];
+    }
+    if (cs2) *cs2 = St::cs2;
+    return LBM_OK;
+  };
+  switch (q) {
+    case 7: return fill(Stencil<7>{});
+    case 15: return fill(Stencil<15>{});
+    case 19: return fill(Stencil<19>{});
+    case 27: return fill(Stencil<27>{});
+    default: set_err(g_err, "no D3Q%d stencil", q); return LBM_EINVAL;
+  }
+}
+
+int lbm_bw_probe(int32_t kind, void* dst, const void* src, size_t bytes, void* hip_stream) {
+  if (bytes == 0 || bytes % 16) { set_err(g_err, "bytes must be a positive multiple of 16"); return LBM_EINVAL; }
+  if (!dst || (kind != 2 && !src)) { set_err(g_err, "NULL buffer"); return LBM_EINVAL; }
+  const int64_t nv = (int64_t)(bytes / 16);
+  const int blocks = 256 * 32;   // 32 blocks per CU of 256 threads, grid-stride
+  hipStream_t st = (hipStream_t)hip_stream;
+  switch (kind) {
+    case 0: hipLaunchKernelGGL(bw_copy_kernel, dim3(blocks), dim3(256), 0, st, (v4f*)dst, (const v4f*)src, nv); break;
+    case 1: hipLaunchKernelGGL(bw_read_kernel, dim3(blocks), dim3(256), 0, st, (float*)dst, (const v4f*)src, nv); break;
+    case 2: hipLaunchKernelGGL(bw_write_kernel, dim3(blocks), dim3(256), 0, st, (v4f*)dst, nv); break;
+    default: set_err(g_err, "kind = %d invalid", kind); return LBM_EINVAL;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(nullptr, e, "bandwidth probe");
+  return LBM_OK;
+}
+
+int64_t lbm_get_step(const lbm_ctx* c) { return c ? c->step : -1; }
+
+const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err : g_err; }
+
+const char* lbm_status_string(int s) {
+  switch (s) {
+    case LBM_OK: return "LBM_OK";
+    case LBM_EINVAL: return "LBM_EINVAL";
+    case LBM_ESIZE: return "LBM_ESIZE";
+    case LBM_EHIP: return "LBM_EHIP";
+    case LBM_EUNSTABLE: return "LBM_EUNSTABLE";
+    case LBM_ESTATE: return "LBM_ESTATE";
+    default: return "unknown status";
+  }
+}
+
+void lbm_destroy(lbm_ctx* c) { delete c; }
+
+}  // extern "C"

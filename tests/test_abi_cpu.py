@@ -1,0 +1,90 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point of
+include/stgv.h, validates parameters on the CPU, and its stencil tables and
+derived constants agree with the oracle's independent ones."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import lattice as lat, model
+
+stgv = pytest.importorskip("paper_2605_14505_amd.stgv", reason="libstgv.so not built")
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "stgv.h")
+
+
+def test_library_exports_every_declared_entry_point():
+    text = open(HEADER).read()
+    declared = set(re.findall(r"^\s*(?:int|int64_t|void|const char\*)\s+(lbm_\w+)\s*\(", text, re.M))
+    assert declared, "no declarations parsed"
+    assert declared == set(stgv.EXPORTED)
+    for name in declared:
+        assert hasattr(stgv.LIB, name)
+
+
+@pytest.mark.parametrize("q", [7, 15, 19, 27])
+def test_stencil_tables_match_oracle(q):
+    e, w, cs2 = stgv.lbm_stencil_info(q)
+    L = lat.BY_Q[q]
+    assert [tuple(v) for v in L.e] == e
+    np.testing.assert_array_equal(np.array(w), L.w)
+    assert cs2 == L.cs2
+
+
+@pytest.mark.parametrize("q_f,q_g", [(27, 19), (27, 7), (19, 7)])
+@pytest.mark.parametrize("fr", [0.3, 1.0, math.inf])
+def test_derived_constants_match_oracle(q_f, q_g, fr):
+    p = stgv.make_params(n=256, q_f=q_f, q_g=q_g, u0=0.05, re=1600, fr=fr, sc=0.7, g_over_n=0.5)
+    d = stgv.lbm_derived(p)
+    U = model.units(model.Params(n=256, q_f=q_f, q_g=q_g, u0=0.05, re=1600, fr=fr, sc=0.7, g_over_n=0.5))
+    for k in ("L", "nu", "D", "tau_f", "tau_g", "nb", "G", "beta"):
+        assert d[k] == pytest.approx(getattr(U, k), rel=1e-14, abs=0), k
+
+
+def test_query_sizes():
+    p = stgv.make_params(n=64)
+    pop, work = stgv.lbm_query_sizes(p)
+    n3 = 64 ** 3
+    assert pop >= 46 * n3 * 4 and pop < 46 * (n3 + 4096) * 4
+    assert work >= 5 * n3 * 4
+    p16 = stgv.make_params(n=64, storage="fp16")
+    assert stgv.lbm_query_sizes(p16)[0] * 2 == pytest.approx(pop, rel=0.01)
+    pab = stgv.make_params(n=64, layout="ab")
+    assert stgv.lbm_query_sizes(pab)[0] == 2 * pop
+    p7 = stgv.make_params(n=64, q_f=19, q_g=7)
+    assert stgv.lbm_query_sizes(p7)[0] < pop
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n=3), dict(n=1025), dict(q_f=27, q_g=27), dict(q_f=15, q_g=7), dict(forcing=7),
+    dict(storage=5), dict(layout=3), dict(diag_every=-1), dict(u0=0.0), dict(u0=0.5),
+    dict(u0=float("nan")), dict(re=0.0), dict(re=-5.0), dict(sc=0.0), dict(fr=0.0),
+    dict(fr=float("nan")), dict(g_over_n=0.0), dict(g_over_n=float("inf")), dict(noise_amp=-1.0),
+])
+def test_invalid_parameters_are_rejected_on_the_cpu(bad):
+    p = stgv.make_params(**{"n": 32, **bad})
+    with pytest.raises(stgv.LbmError) as ei:
+        stgv.lbm_query_sizes(p)
+    assert ei.value.status == stgv.LBM_EINVAL
+    assert str(ei.value)
+
+
+def test_unstratified_limit_has_no_gravity():
+    d = stgv.lbm_derived(stgv.make_params(n=32, fr=math.inf))
+    assert d["nb"] == 0.0 and d["G"] == 0.0 and d["beta"] == 0.0
+
+
+def test_null_arguments():
+    import ctypes
+    assert stgv.LIB.lbm_step(None, 1) == stgv.LBM_EINVAL
+    assert stgv.LIB.lbm_diagnostics(None, None, 0, None) == stgv.LBM_EINVAL
+    assert stgv.LIB.lbm_query_sizes(None, None, None) == stgv.LBM_EINVAL
+    p = stgv.make_params(n=32)
+    out = ctypes.c_void_p()
+    # null device buffers are rejected before any HIP call
+    assert stgv.LIB.lbm_init_tgv(ctypes.byref(p), None, 0, None, 0, None, ctypes.byref(out)) == stgv.LBM_EINVAL
+    assert stgv.LIB.lbm_bw_probe(0, None, None, 17, None) == stgv.LBM_EINVAL
+    assert stgv.LIB.lbm_stencil_info(9, None, None, None) == stgv.LBM_EINVAL
+    stgv.LIB.lbm_destroy(None)

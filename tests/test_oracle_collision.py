@@ -147,3 +147,28 @@ def test_vectorised_step_matches_node_by_node_transcription(q_f, q_g, forcing):
     fm, gm = micro.step(f.tolist(), g.tolist(), q_f, q_g, U.tau_f, U.tau_g, U.G, U.beta, forcing)
     np.testing.assert_allclose(np.array(fm), fv, rtol=1e-14, atol=0)
     np.testing.assert_allclose(np.array(gm), gv, rtol=1e-14, atol=0)
+
+
+def test_storage_rounding_is_round_to_nearest_even():
+    # bfloat16 has an 8-bit significand: 1 + 2^-8 is the midpoint between 1 and 1 + 2^-7
+    assert model.round_to_bf16(np.array([1.0 + 2.0 ** -8]))[0] == 1.0                     # tie -> even
+    assert model.round_to_bf16(np.array([1.0 + 3 * 2.0 ** -8]))[0] == 1.0 + 2.0 ** -6      # tie -> even
+    assert model.round_to_bf16(np.array([1.0 + 2.0 ** -8 + 2.0 ** -20]))[0] == 1.0 + 2.0 ** -7
+    assert model.round_to_bf16(np.array([-3.0e-3]))[0] == -0.0030059814453125
+    x = np.random.default_rng(9).standard_normal(1000) * 1e-2
+    r = model.round_to_bf16(x)
+    # same as truncating a correctly rounded value to 8 significant bits: at most half a unit
+    _, e = np.frexp(x)
+    assert np.all(np.abs(r - x) <= np.ldexp(0.5, e - 8))
+    assert model.round_storage(np.array([1.0 + 2.0 ** -11]), "fp16")[0] == 1.0             # fp16 tie
+    assert model.round_storage(np.array([0.1]), "fp32")[0] == float(np.float32(0.1))
+
+
+def test_fp64_storage_is_the_plain_oracle():
+    p = model.Params(n=6, forcing="shift", re=100, noise_amp=1e-3)
+    (f1, g1), _ = model.run(p, 3)
+    (f2, g2), _ = model.run(p, 3, storage="fp64")
+    np.testing.assert_array_equal(f1, f2)
+    np.testing.assert_array_equal(g1, g2)
+    (f3, _), _ = model.run(p, 3, storage="fp16")
+    assert 0 < np.abs(f3 - f1).max() < 1e-4
