@@ -16,7 +16,6 @@ taken on the current kernel sources, the FP64 oracle timed on the host cores,
 and the energy error of the GPU against the oracle on the 32^3 parity case.
 """
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -25,16 +24,6 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 PEAK_HBM_GBS = 8000.0
-
-
-def kernel_source_hash():
-    csrc = os.path.join(ROOT, "paper_2605_14505_amd", "csrc")
-    h = hashlib.sha256()
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp")):
-            h.update(f.encode())
-            h.update(open(os.path.join(csrc, f), "rb").read())
-    return h.hexdigest()[:16]
 
 
 def read_traffic(workload_key, n3, bytes_per_node):
@@ -47,6 +36,7 @@ def read_traffic(workload_key, n3, bytes_per_node):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
+    from paper_2605_14505_amd.profsummary import kernel_source_hash
     if kv.get("source_hash") != kernel_source_hash():
         return None, "counters predate the current kernel sources"
     try:

@@ -159,7 +159,7 @@ int lbm_load_populations(lbm_ctx* ctx, const float* dev_in, int64_t step);
 int lbm_stencil_info(int32_t q, int32_t* e, double* w, double* cs2);
 
 /* Streaming-bandwidth probe: kind 0 copies `bytes` from src to dst, kind 1
- * reads src (one float per block written to dst), kind 2 writes dst.
+ * reads src (writes one float per 16 KiB of src to dst), kind 2 writes dst.
  * Queued on hip_stream; bytes must be a multiple of 16. */
 int lbm_bw_probe(int32_t kind, void* dst, const void* src, size_t bytes, void* hip_stream);
 

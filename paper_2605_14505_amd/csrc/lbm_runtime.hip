@@ -129,25 +129,41 @@ __global__ __launch_bounds__(256) void lbm_final_kernel(const double* __restrict
 }
 
 // ---------------------------------------------------------------------------
-// Streaming-bandwidth probe: the achievable HBM ceiling for the step's pattern
-// of long unit-stride streams.  Grid-stride loops over 16-byte vectors.
+// Streaming-bandwidth probe: the achievable HBM ceiling for long unit-stride
+// streams.  Each 256-thread block moves one 16 KiB chunk: four coalesced
+// 16-byte vectors per thread, all loads issued before the stores.
 // ---------------------------------------------------------------------------
 typedef float v4f __attribute__((ext_vector_type(4)));
+constexpr int BW_UNROLL = 4;
 
 __global__ __launch_bounds__(256) void bw_copy_kernel(v4f* __restrict__ dst,
                                                       const v4f* __restrict__ src, int64_t nv) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nv;
-       i += (int64_t)gridDim.x * blockDim.x)
-    __builtin_nontemporal_store(src[i], dst + i);
+  const int64_t base = (int64_t)blockIdx.x * (256 * BW_UNROLL) + threadIdx.x;
+  v4f v[BW_UNROLL];
+#pragma unroll
+  for (int k = 0; k < BW_UNROLL; ++k) {
+    const int64_t i = base + k * 256;
+    if (i < nv) v[k] = __builtin_nontemporal_load(src + i);
+  }
+#pragma unroll
+  for (int k = 0; k < BW_UNROLL; ++k) {
+    const int64_t i = base + k * 256;
+    if (i < nv) __builtin_nontemporal_store(v[k], dst + i);
+  }
 }
 __global__ __launch_bounds__(256) void bw_read_kernel(float* __restrict__ dst,
                                                       const v4f* __restrict__ src, int64_t nv) {
+  const int64_t base = (int64_t)blockIdx.x * (256 * BW_UNROLL) + threadIdx.x;
   float acc = 0.f;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nv;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const v4f v = src[i];
-    acc += v.x + v.y + v.z + v.w;
+#pragma unroll
+  for (int k = 0; k < BW_UNROLL; ++k) {
+    const int64_t i = base + k * 256;
+    if (i < nv) {
+      const v4f v = __builtin_nontemporal_load(src + i);
+      acc += v.x + v.y + v.z + v.w;
+    }
   }
+  // keep the loads live; one value per block
   __shared__ float red[256];
   red[threadIdx.x] = acc;
   __syncthreads();
@@ -158,10 +174,13 @@ __global__ __launch_bounds__(256) void bw_read_kernel(float* __restrict__ dst,
   if (threadIdx.x == 0) dst[blockIdx.x] = red[0];
 }
 __global__ __launch_bounds__(256) void bw_write_kernel(v4f* __restrict__ dst, int64_t nv) {
+  const int64_t base = (int64_t)blockIdx.x * (256 * BW_UNROLL) + threadIdx.x;
   const v4f v = {0.f, 0.f, 0.f, 0.f};
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nv;
-       i += (int64_t)gridDim.x * blockDim.x)
-    __builtin_nontemporal_store(v, dst + i);
+#pragma unroll
+  for (int k = 0; k < BW_UNROLL; ++k) {
+    const int64_t i = base + k * 256;
+    if (i < nv) __builtin_nontemporal_store(v, dst + i);
+  }
 }
 
 }  // namespace stgv
@@ -627,7 +646,8 @@ int lbm_bw_probe(int32_t kind, void* dst, const void* src, size_t bytes, void* h
   if (bytes == 0 || bytes % 16) { set_err(g_err, "bytes must be a positive multiple of 16"); return LBM_EINVAL; }
   if (!dst || (kind != 2 && !src)) { set_err(g_err, "NULL buffer"); return LBM_EINVAL; }
   const int64_t nv = (int64_t)(bytes / 16);
-  const int blocks = 256 * 32;   // 32 blocks per CU of 256 threads, grid-stride
+  const int64_t blocks = (nv + 256 * BW_UNROLL - 1) / (256 * BW_UNROLL);
+  if (blocks > 0x7fffffff) { set_err(g_err, "bytes too large"); return LBM_EINVAL; }
   hipStream_t st = (hipStream_t)hip_stream;
   switch (kind) {
     case 0: hipLaunchKernelGGL(bw_copy_kernel, dim3(blocks), dim3(256), 0, st, (v4f*)dst, (const v4f*)src, nv); break;
