@@ -69,10 +69,21 @@ struct Geometry {
 // ---------------------------------------------------------------------------
 struct bf16_t { uint16_t bits; };
 
-template <typename C> __device__ __forceinline__ C load_as(const float* p) { return (C)(*p); }
-template <typename C> __device__ __forceinline__ C load_as(const _Float16* p) { return (C)(float)(*p); }
+#ifndef STGV_NT_LOAD
+#define STGV_NT_LOAD 0
+#endif
+template <typename T>
+__device__ __forceinline__ T get(const T* p) {
+#if STGV_NT_LOAD
+  return __builtin_nontemporal_load(p);
+#else
+  return *p;
+#endif
+}
+template <typename C> __device__ __forceinline__ C load_as(const float* p) { return (C)get(p); }
+template <typename C> __device__ __forceinline__ C load_as(const _Float16* p) { return (C)(float)get(p); }
 template <typename C> __device__ __forceinline__ C load_as(const bf16_t* p) {
-  return (C)__uint_as_float(((uint32_t)p->bits) << 16);
+  return (C)__uint_as_float(((uint32_t)get(&p->bits)) << 16);
 }
 
 __device__ __forceinline__ uint16_t float_to_bf16_rne(float v) {
@@ -81,14 +92,25 @@ __device__ __forceinline__ uint16_t float_to_bf16_rne(float v) {
   u += 0x7fffu + ((u >> 16) & 1u);
   return (uint16_t)(u >> 16);
 }
+// Population stores bypass the caches by default (each value is read again only
+// one step later, after the whole ~GB state has streamed through).
+#ifndef STGV_NT_STORE
+#define STGV_NT_STORE 1
+#endif
+template <typename T>
+__device__ __forceinline__ void put(T* p, T v) {
+#if STGV_NT_STORE
+  __builtin_nontemporal_store(v, p);
+#else
+  *p = v;
+#endif
+}
 // Rounding to the storage type is round-to-nearest-even in every case (a double
 // is rounded once, straight to FP32; FP16 / BF16 stores take FP32 values).
-__device__ __forceinline__ void store_as(float* p, float v) { __builtin_nontemporal_store(v, p); }
-__device__ __forceinline__ void store_as(float* p, double v) { __builtin_nontemporal_store((float)v, p); }
-__device__ __forceinline__ void store_as(_Float16* p, float v) { __builtin_nontemporal_store((_Float16)v, p); }
-__device__ __forceinline__ void store_as(bf16_t* p, float v) {
-  __builtin_nontemporal_store(float_to_bf16_rne(v), &p->bits);
-}
+__device__ __forceinline__ void store_as(float* p, float v) { put(p, v); }
+__device__ __forceinline__ void store_as(float* p, double v) { put(p, (float)v); }
+__device__ __forceinline__ void store_as(_Float16* p, float v) { put(p, (_Float16)v); }
+__device__ __forceinline__ void store_as(bf16_t* p, float v) { put(&p->bits, float_to_bf16_rne(v)); }
 
 // ---------------------------------------------------------------------------
 // neighbour addressing on the periodic box

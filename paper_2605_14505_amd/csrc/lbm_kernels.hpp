@@ -11,8 +11,19 @@ namespace stgv {
 // `pop` is the population array (AA) or the source lattice (AB); `dst` is the
 // AB destination and equals `pop` otherwise.
 // ---------------------------------------------------------------------------
+// Minimum resident 256-thread blocks per CU requested from the register allocator
+// (0 = compiler's choice).
+#ifndef STGV_STEP_MIN_BLOCKS
+#define STGV_STEP_MIN_BLOCKS 0
+#endif
+#if STGV_STEP_MIN_BLOCKS > 0
+#define STGV_STEP_BOUNDS __launch_bounds__(256, STGV_STEP_MIN_BLOCKS)
+#else
+#define STGV_STEP_BOUNDS __launch_bounds__(256)
+#endif
+
 template <int QF, int QG, int FORCE, typename T, typename C, int MODE, int FLAGS>
-__global__ __launch_bounds__(256) void lbm_step_kernel(T* pop, T* dst, Geometry geo,
+__global__ STGV_STEP_BOUNDS void lbm_step_kernel(T* pop, T* dst, Geometry geo,
                                                        PhysConsts c, float* __restrict__ fields,
                                                        double* __restrict__ partials) {
   const int n = geo.n;

@@ -14,6 +14,9 @@ struct LaunchShape {
 // Launch shape of the node kernels: block (bx, by) over x and y, grid over
 // (x, y, z).  Blocks are 256 threads except when a row is shorter than a
 // wavefront; every block is a whole number of 64-wide wavefronts.
+#ifndef STGV_BLOCK_X
+#define STGV_BLOCK_X 256
+#endif
 inline LaunchShape node_shape(int n) {
   int bx, by;
   if (n <= 64 && 64 % n == 0) {
@@ -21,7 +24,7 @@ inline LaunchShape node_shape(int n) {
     by = 256 / n;
   } else {
     bx = ((n + 63) / 64) * 64;
-    if (bx > 256) bx = 256;
+    if (bx > STGV_BLOCK_X) bx = STGV_BLOCK_X;
     by = 256 / bx;
   }
   LaunchShape s;

@@ -12,7 +12,8 @@ import os
 import torch  # loads the HIP runtime the library then shares
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "lib", "libstgv.so")
+# STGV_LIB selects another build of the same library (e.g. one compiled with tuning macros)
+LIB_PATH = os.environ.get("STGV_LIB") or os.path.join(_HERE, "lib", "libstgv.so")
 
 LBM_OK, LBM_EINVAL, LBM_ESIZE, LBM_EHIP, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 LBM_FORCE_GUO, LBM_FORCE_SHIFT = 0, 1
