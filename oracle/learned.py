@@ -77,13 +77,21 @@ def moment_inverse(q):
 # features and the correction
 # ----------------------------------------------------------------------------
 def features(f, g, U: model.Units):
-    """(47, ...) non-equilibrium moments of f and g at the collision's equilibria, and rho'."""
+    """(47, ...) non-equilibrium moments of f and g at the collision's equilibria, and rho'.
+
+    The conserved slots hold their exact values rather than the rounding residue of the
+    sums: the equilibria carry the mass rho, the momentum rho u_eq and the scalar
+    rho' + rho_0 by construction (Eqs. (6), (7), (10), (16)), so those moments of
+    f - f^eq and g - g^eq are 0, rho (u' - u_eq) and sum(g) - rho' - rho_0."""
     lf, lg = lat.D3Q27, lat.D3Q19
     m = model.macro(f, g, lf, lg, U)
     feq = model.f_equilibrium(lf, m.rho, m.ueq)
     geq = (m.rho_p + model.RHO0) * model.theta(lg, m.ueq)
     mf = np.tensordot(moment_matrix(27).astype(np.float64), f - feq, axes=(1, 0))
     mg = np.tensordot(moment_matrix(19).astype(np.float64), g - geq, axes=(1, 0))
+    mf[0] = 0.0
+    mf[1:4] = m.rho * (m.up - m.ueq)
+    mg[0] = m.sigma - m.rho_p - model.RHO0
     return np.concatenate([mf, mg, m.rho_p[None]])
 
 
@@ -250,13 +258,30 @@ def unstream(pop, L):
     return out
 
 
+def pairs_from(a, b, c, pc: model.Params):
+    """Features of state a and targets from b - c returned to the source node and projected."""
+    lf, lg = lat.D3Q27, lat.D3Q19
+    x = features(a[0], a[1], model.units(pc))
+    y = project(unstream(b[0] - c[0], lf), unstream(b[1] - c[1], lg))
+    return x, y
+
+
 def training_pair(a, b, pc: model.Params):
     """Features at the coarse state a = (f, g) and targets toward b (the restricted state one
     coarse step later): the residual of one coarse step, un-streamed and projected."""
     lf, lg = lat.D3Q27, lat.D3Q19
     U = model.units(pc)
-    x = features(a[0], a[1], U)
     fs, gs, _ = model.collide(a[0], a[1], lf, lg, U)
-    cf, cg = model.stream(fs, lf), model.stream(gs, lg)
-    y = project(unstream(b[0] - cf, lf), unstream(b[1] - cg, lg))
-    return x, y
+    return pairs_from(a, b, (model.stream(fs, lf), model.stream(gs, lg)), pc)
+
+
+def norm_from_data(x, y):
+    """(x_mean, x_iscale, y_scale) of rows x (n, 47), y (n, 41): mean, 1/std (0 for a constant
+    column) and root mean square (1 if zero)."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    mean = x.mean(0)
+    var = (x * x).mean(0) - mean * mean
+    iscale = np.where(var > 1e-300, 1.0 / np.sqrt(np.maximum(var, 1e-300)), 0.0)
+    ms = (y * y).mean(0)
+    return mean, iscale, np.where(ms > 1e-300, np.sqrt(np.maximum(ms, 1e-300)), 1.0)

@@ -134,3 +134,24 @@ def test_training_targets_vanish_for_an_exact_coarse_step():
     cf, cg = L.correction(dm)
     _, y2 = L.training_pair(a, (b_f + model.stream(cf, lat.D3Q27), b_g + model.stream(cg, lat.D3Q19)), pc)
     np.testing.assert_allclose(y2, dm, rtol=1e-7, atol=1e-16)
+
+
+@pytest.mark.parametrize("forcing", ["guo", "shift"])
+def test_conserved_feature_slots_are_the_full_moments(forcing):
+    # the closed forms of the conserved slots agree with the moments of f - f^eq, g - g^eq
+    # summed in full, and carry the forcing: -F_z/2 (Guo) or -tau_f F_z (shift)
+    p = model.Params(n=6, forcing=forcing, re=100, fr=0.5, noise_amp=1e-3, g_over_n=0.5)
+    (f, g), _ = model.run(p, 3)
+    U = model.units(p)
+    x = L.features(f, g, U)
+    m = model.macro(f, g, lat.D3Q27, lat.D3Q19, U)
+    feq = model.f_equilibrium(lat.D3Q27, m.rho, m.ueq)
+    geq = (m.rho_p + model.RHO0) * model.theta(lat.D3Q19, m.ueq)
+    e = lat.D3Q27.e.astype(float)
+    np.testing.assert_allclose(x[0], (f - feq).sum(0), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(x[1:4], np.tensordot(e.T, f - feq, axes=(1, 0)), rtol=0, atol=1e-16)
+    np.testing.assert_allclose(x[27], (g - geq).sum(0), rtol=0, atol=1e-15)
+    fz = -U.G * m.rho_p
+    np.testing.assert_allclose(x[3], -0.5 * fz if forcing == "guo" else -U.tau_f * fz, rtol=1e-9)
+    np.testing.assert_allclose(x[27], -0.5 * m.s, rtol=1e-9, atol=1e-18)
+    assert np.abs(x[3]).max() > 0 and np.all(x[0:3] == 0.0)
