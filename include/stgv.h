@@ -163,6 +163,76 @@ int lbm_stencil_info(int32_t q, int32_t* e, double* w, double* cs2);
  * Queued on hip_stream; bytes must be a multiple of 16. */
 int lbm_bw_probe(int32_t kind, void* dst, const void* src, size_t bytes, void* hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Learned correction of a coarse D3Q27 x D3Q19 run (this library's extension of
+ * the method; not in the paper).  A per-node network maps 47 features (the
+ * non-equilibrium moments M (f - f^eq), M (g - g^eq) in the monomial basis
+ * e_x^a e_y^b e_z^c, a, b, c in {0, 1, 2}, and rho') to corrections dm of the 41
+ * non-conserved moments; the post-collision populations gain M^-1 [0, dm], which
+ * leaves mass, momentum and the scalar untouched.  Network 47 -> 64 -> 64 -> 41,
+ * tanh, BF16 MFMA with FP32 accumulation.
+ *
+ * Parameters ("params", LBM_MLP_PARAMS FP32 on the device, the master copy):
+ * W1 [64][47], b1 [64], W2 [64][64], b2 [64], W3 [41][64], b3 [41], row-major.
+ * Normalisation ("norm", 135 FP32): x_mean [47], x_iscale [47], y_scale [41];
+ * the network sees (x - x_mean) * x_iscale and its output times y_scale is dm.
+ * Feature rows are [rows][47] FP32, target rows [rows][41] FP32.  All buffers
+ * are caller-owned device memory; work is queued on hip_stream.
+ * ------------------------------------------------------------------------ */
+enum { LBM_MLP_IN = 47, LBM_MLP_HIDDEN = 64, LBM_MLP_OUT = 41, LBM_MLP_PARAMS = 9897,
+       LBM_MLP_NORM = 135 };
+
+/* Bytes of the packed network (BF16 weight tiles, FP32 biases and normalisation). */
+size_t lbm_mlp_packed_bytes(void);
+
+/* Pack params + norm into packed_dev (>= lbm_mlp_packed_bytes(), 16-byte aligned). */
+int lbm_mlp_pack(const float* params_dev, const float* norm_dev, void* packed_dev, void* hip_stream);
+
+/* dm for `rows` feature rows (de-normalised network output). */
+int lbm_mlp_forward(const void* packed_dev, const float* x_dev, int64_t rows, float* y_dev,
+                    void* hip_stream);
+
+/* Work bytes of lbm_mlp_grad for a batch. */
+size_t lbm_mlp_grad_work_bytes(int64_t batch);
+
+/* Gradient (LBM_MLP_PARAMS FP32, parameter order) and loss (one FP64) of the mean
+ * squared error between the normalised output and y / y_scale over the batch
+ * rows idx_dev[0..batch) of x_dev / y_dev.  Deterministic (fixed-order sums). */
+int lbm_mlp_grad(const void* packed_dev, const float* x_dev, const float* y_dev,
+                 const int64_t* idx_dev, int64_t batch, float* grad_dev, double* loss_dev,
+                 void* work_dev, size_t work_bytes, void* hip_stream);
+
+/* One Adam step (Kingma & Ba; beta1 0.9, beta2 0.999, eps 1e-8) at step t >= 1 on
+ * params / m / v (FP32, LBM_MLP_PARAMS each). */
+int lbm_mlp_adam(float* params_dev, float* m_dev, float* v_dev, const float* grad_dev, int64_t t,
+                 double lr, void* hip_stream);
+
+/* Normalisation from data: x_mean, x_iscale = 1 / std (0 for a constant
+ * column), y_scale = root mean square (1 if zero), over `rows` rows. */
+size_t lbm_mlp_norm_work_bytes(void);
+int lbm_mlp_norm(const float* x_dev, const float* y_dev, int64_t rows, float* norm_dev,
+                 void* work_dev, size_t work_bytes, void* hip_stream);
+
+/* Restrict the current state of a fine D3Q27 x D3Q19 context to the grid of a
+ * coarse one (fine n = 4 coarse n): separable [1,2,2,2,1]/8 filter sampled at
+ * every 4th node, non-conserved filtered non-equilibrium moments rescaled by
+ * 4 tau_coarse / tau_fine.  coarse_dev: (q_f + q_g) n_c^3 FP32 deviations in the
+ * layout of lbm_read_populations.  Queued on the fine context's stream. */
+int lbm_restrict(lbm_ctx* fine, const lbm_ctx* coarse, float* coarse_dev);
+
+/* Training pairs on a coarse grid: features x_dev [n^3][47] of state a_dev and
+ * targets y_dev [n^3][41]: the non-conserved moments of (b - c) returned to the
+ * node each population streamed from, where b is the restricted fine state one
+ * coarse step later and c the coarse step of a (all in the layout of
+ * lbm_read_populations).  Queued on the context's stream. */
+int lbm_training_pairs(lbm_ctx* coarse, const float* a_dev, const float* b_dev, const float* c_dev,
+                       float* x_dev, float* y_dev);
+
+/* Attach (or, with NULL, detach) a packed network to a D3Q27 x D3Q19 context
+ * with FP32 storage and arithmetic and n % 64 == 0; later lbm_step calls run
+ * the fused learned step.  packed_dev must stay valid while attached. */
+int lbm_set_mlp(lbm_ctx* ctx, const void* packed_dev);
+
 int64_t lbm_get_step(const lbm_ctx* ctx);
 const char* lbm_last_error(const lbm_ctx* ctx);
 const char* lbm_status_string(int status);

@@ -22,6 +22,10 @@ CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
     # keep the compiler from emitting packed FP32 VALU ops
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # fuse a * b + c only within one source expression: the rounding of every
+    # kernel then follows its source, so two kernels that share the collision
+    # code (the plain and the learned step) round it identically
+    "-ffp-contract=on",
 ]
 
 

@@ -29,6 +29,7 @@ enum KernelFlags : int {
   K_COLLIDE = 1,    // collide and stream (the time step)
   K_FIELDS = 2,     // write rho - 1, u_x, u_y, u_z, rho' per node
   K_PARTIALS = 4,   // write per-block diagnostic partials
+  K_LEARNED = 8,    // add the learned moment correction (D3Q27 x D3Q19, one wavefront per block)
 };
 
 // Per-block diagnostic partials written by the diagnostic step / moments kernels.
@@ -273,6 +274,72 @@ __device__ __forceinline__ void node_macro(const C* f, const C* g, const PhysCon
   else m.vz = upz + (C)c.tau_f * Fz * inv_rho;  // Shan-Chen shift, Eq. (10) (tau F / rho)
 }
 
+template <int QF, int QG, int FORCE, typename C>
+struct Collision {
+  using SF = Stencil<QF>;
+  using SG = Stencil<QG>;
+  static constexpr C icf = C(1.0 / SF::cs2);
+  static constexpr C icg = C(1.0 / SG::cs2);
+  const NodeMacro<C>& m;
+  C vx, vy, vz, usq, omega_f, omega_g, tau_f, base_f, conc, base_g;
+
+  __device__ __forceinline__ Collision(const PhysConsts& c, const NodeMacro<C>& mm) : m(mm) {
+    vx = m.vx; vy = m.vy; vz = m.vz;
+    usq = vx * vx + vy * vy + vz * vz;
+    omega_f = (C)c.omega_f; omega_g = (C)c.omega_g; tau_f = (C)c.tau_f;
+    base_f = m.drho - C(0.5) * icf * m.rho * usq;
+    conc = C(1) + m.rho_p;
+    base_g = -C(0.5) * icg * usq;
+  }
+  // momentum lattice: df_eq = w [drho + rho (xi + xi^2/2 - u^2/(2 c^2))], xi = e.u / c^2
+  __device__ __forceinline__ C feq(int i) const {
+    const C xi = icf * dot_e(SF::ex[i], SF::ey[i], SF::ez[i], vx, vy, vz);
+    return C(SF::w[i]) * (base_f + m.rho * xi * (C(1) + C(0.5) * xi));
+  }
+  // scalar lattice: dg_eq = w [rho' + (1 + rho') (xi + xi^2/2 - u^2/(2 c^2))]
+  __device__ __forceinline__ C geq(int j) const {
+    const C xi = icg * dot_e(SG::ex[j], SG::ey[j], SG::ez[j], vx, vy, vz);
+    return C(SG::w[j]) * (m.rho_p + conc * (base_g + xi * (C(1) + C(0.5) * xi)));
+  }
+  // f[i] <- d_i = f_i^eq - f_i and g[j] <- h_j = g_j^eq - g_j
+  __device__ __forceinline__ void relaxation_increments(C* f, C* g) const {
+#pragma unroll
+    for (int i = 0; i < QF; ++i) f[i] = feq(i) - f[i];
+#pragma unroll
+    for (int j = 0; j < QG; ++j) g[j] = geq(j) - g[j];
+  }
+  // From the increments to the post-collision populations.
+  //   f*_i = f_i + omega (d_i - p_i) + G_i = f_i^eq + [(omega - 1) d_i - omega p_i + G_i]
+  // with p_i = w_i (r_0 + e_i . r / c^2) the projection of the moment residual
+  // and G_i the Guo term; the bracket is formed with fused multiply-adds so the
+  // small terms (p_i, G_i ~ 1e-12) shift its single rounding instead of
+  // deciding ties of the final sum: ties broken by a term whose sign follows
+  // e_i . F would bias the node mass a little every step.
+  __device__ __forceinline__ void finish(C* f, C* g) const {
+    C r0, rx, ry, rz;
+    pair_moments<QF>(f, r0, rx, ry, rz);
+    rz -= (FORCE == FORCE_GUO) ? C(0.5) * m.Fz : tau_f * m.Fz;
+    const C guo_c = (FORCE == FORCE_GUO) ? (C(1) - C(0.5) * omega_f) * m.Fz : C(0);
+#pragma unroll
+    for (int i = 0; i < QF; ++i) {
+      const C p = C(SF::w[i]) * (r0 + icf * dot_e(SF::ex[i], SF::ey[i], SF::ez[i], rx, ry, rz));
+      C small = -omega_f * p;
+      if (FORCE == FORCE_GUO) {
+        // Guo term with F = (0, 0, Fz): (1 - omega/2) w [(e_z - u_z) / c^2 + (e.u) e_z / c^4] Fz
+        const C eu = dot_e(SF::ex[i], SF::ey[i], SF::ez[i], vx, vy, vz);
+        C br = -icf * m.uz;
+        if (SF::ez[i] != 0) br += SF::ez[i] > 0 ? icf * (C(1) + icf * eu) : -icf * (C(1) + icf * eu);
+        small = fma_c(-omega_f, p, C(SF::w[i]) * guo_c * br);
+      }
+      f[i] = feq(i) + fma_c(omega_f - C(1), f[i], small);
+    }
+    const C r0g = pair_sum<QG>(g) - C(0.5) * m.s;
+    const C src = (C(1) - C(0.5) * omega_g) * m.s - omega_g * r0g;
+#pragma unroll
+    for (int j = 0; j < QG; ++j) g[j] = geq(j) + fma_c(omega_g - C(1), g[j], C(SG::w[j]) * src);
+  }
+};
+
 // BGK collision of both lattices in place (Eqs. (5), (8), (9), (11), (14), (15)).
 //
 // The relaxation increment d_i = f_i^eq - f_i has, in exact arithmetic, zeroth
@@ -286,58 +353,9 @@ __device__ __forceinline__ void node_macro(const C* f, const C* g, const PhysCon
 template <int QF, int QG, int FORCE, typename C>
 __device__ __forceinline__ void node_collide(C* f, C* g, const PhysConsts& c,
                                              const NodeMacro<C>& m) {
-  using SF = Stencil<QF>;
-  using SG = Stencil<QG>;
-  const C vx = m.vx, vy = m.vy, vz = m.vz;
-  const C usq = vx * vx + vy * vy + vz * vz;
-  const C omega_f = (C)c.omega_f, omega_g = (C)c.omega_g;
-  // momentum lattice: df_eq = w [drho + rho (xi + xi^2/2 - u^2/(2 c^2))], xi = e.u / c^2
-  constexpr C icf = C(1.0 / SF::cs2);
-  const C base_f = m.drho - C(0.5) * icf * m.rho * usq;
-  auto feq = [&](int i) {
-    const C xi = icf * dot_e(SF::ex[i], SF::ey[i], SF::ez[i], vx, vy, vz);
-    return C(SF::w[i]) * (base_f + m.rho * xi * (C(1) + C(0.5) * xi));
-  };
-  // f[i] <- d_i = f_i^eq - f_i (so f_i = f_i^eq - d_i below)
-#pragma unroll
-  for (int i = 0; i < QF; ++i) f[i] = feq(i) - f[i];
-  C r0, rx, ry, rz;
-  pair_moments<QF>(f, r0, rx, ry, rz);
-  rz -= (FORCE == FORCE_GUO) ? C(0.5) * m.Fz : (C)c.tau_f * m.Fz;
-  const C guo_c = (FORCE == FORCE_GUO) ? (C(1) - C(0.5) * omega_f) * m.Fz : C(0);
-  // f*_i = f_i + omega (d_i - p_i) + G_i = f_i^eq + [(omega - 1) d_i - omega p_i + G_i],
-  // p_i = w_i (r_0 + e_i . r / c^2) the projection of the moment residual and G_i
-  // the Guo term.  The bracket is formed with fused multiply-adds so that the
-  // small terms (p_i, G_i ~ 1e-12) shift its single rounding instead of
-  // deciding ties of the final sum: ties broken by a term whose sign follows
-  // e_i . F would bias the node mass a little every step.
-#pragma unroll
-  for (int i = 0; i < QF; ++i) {
-    const C p = C(SF::w[i]) * (r0 + icf * dot_e(SF::ex[i], SF::ey[i], SF::ez[i], rx, ry, rz));
-    C small = -omega_f * p;
-    if (FORCE == FORCE_GUO) {
-      // Guo term with F = (0, 0, Fz): (1 - omega/2) w [(e_z - u_z) / c^2 + (e.u) e_z / c^4] Fz
-      const C eu = dot_e(SF::ex[i], SF::ey[i], SF::ez[i], vx, vy, vz);
-      C br = -icf * m.uz;
-      if (SF::ez[i] != 0) br += SF::ez[i] > 0 ? icf * (C(1) + icf * eu) : -icf * (C(1) + icf * eu);
-      small = fma_c(-omega_f, p, C(SF::w[i]) * guo_c * br);
-    }
-    f[i] = feq(i) + fma_c(omega_f - C(1), f[i], small);
-  }
-  // scalar lattice: dg_eq = w [rho' + (1 + rho') (xi + xi^2/2 - u^2/(2 c^2))]
-  constexpr C icg = C(1.0 / SG::cs2);
-  const C conc = C(1) + m.rho_p;
-  const C base_g = -C(0.5) * icg * usq;
-  auto geq = [&](int j) {
-    const C xi = icg * dot_e(SG::ex[j], SG::ey[j], SG::ez[j], vx, vy, vz);
-    return C(SG::w[j]) * (m.rho_p + conc * (base_g + xi * (C(1) + C(0.5) * xi)));
-  };
-#pragma unroll
-  for (int j = 0; j < QG; ++j) g[j] = geq(j) - g[j];
-  const C r0g = pair_sum<QG>(g) - C(0.5) * m.s;
-  const C src = (C(1) - C(0.5) * omega_g) * m.s - omega_g * r0g;
-#pragma unroll
-  for (int j = 0; j < QG; ++j) g[j] = geq(j) + fma_c(omega_g - C(1), g[j], C(SG::w[j]) * src);
+  const Collision<QF, QG, FORCE, C> col(c, m);
+  col.relaxation_increments(f, g);
+  col.finish(f, g);
 }
 
 // ---------------------------------------------------------------------------

@@ -10,8 +10,10 @@
 #include <new>
 
 #include "../../include/stgv.h"
+#include "learned.hpp"
 #include "lbm_device.hpp"
 #include "lbm_launch.hpp"
+#include "mlp_device.hpp"
 
 namespace stgv {
 
@@ -277,7 +279,7 @@ struct Sizes {
   int64_t n3, stride;
   size_t elem, pop_bytes;
   size_t off_fields, off_sp, off_fp, off_ring, work_bytes;
-  int64_t nsp, nfp;
+  int64_t nsp, nfp, nsp_learned;
 };
 
 size_t elem_size(int storage) { return storage == LBM_FP32 ? 4 : 2; }
@@ -296,10 +298,12 @@ Sizes sizes_of(const lbm_params* p) {
   s.pop_bytes = (size_t)(arrays * s.stride) * s.elem;
   const LaunchShape sh = node_shape(p->n);
   s.nsp = (int64_t)sh.grid.x * sh.grid.y * sh.grid.z;
+  s.nsp_learned = (p->n % 64 == 0) ? (int64_t)(p->n / 64) * p->n * p->n : 0;
+  const int64_t nsp_max = s.nsp > s.nsp_learned ? s.nsp : s.nsp_learned;
   s.nfp = (int64_t)((p->n + FD_TX - 1) / FD_TX) * ((p->n + FD_TY - 1) / FD_TY) * ((p->n + FD_ZC - 1) / FD_ZC);
   size_t off = 0;
   s.off_fields = off; off = align_up(off + (size_t)(5 * s.n3) * sizeof(float), kAlign);
-  s.off_sp = off;     off = align_up(off + (size_t)(s.nsp * NPART) * sizeof(double), kAlign);
+  s.off_sp = off;     off = align_up(off + (size_t)(nsp_max * NPART) * sizeof(double), kAlign);
   s.off_fp = off;     off = align_up(off + (size_t)(s.nfp * NFD) * sizeof(double), kAlign);
   s.off_ring = off;   off = align_up(off + (size_t)kRingCap * NREC * sizeof(double), kAlign);
   s.work_bytes = off;
@@ -323,6 +327,7 @@ struct lbm_ctx {
   int odd;             // AA: the array holds the odd-step layout; AB: pop_b is current
   int64_t ring_head;   // records queued
   int64_t ring_tail;   // records drained
+  const void* mlp;     // attached packed network (learned step) or nullptr
   char err[512];
 };
 
@@ -362,7 +367,7 @@ char* current_array(const lbm_ctx* c) {
 }
 
 // Queue the dissipation stencil and the final reduction into the next ring slot.
-hipError_t queue_record(lbm_ctx* c, int64_t step) {
+hipError_t queue_record(lbm_ctx* c, int64_t step, bool learned) {
   const dim3 fblock(FD_TX, FD_TY, 1);
   const dim3 fgrid((c->p.n + FD_TX - 1) / FD_TX, (c->p.n + FD_TY - 1) / FD_TY,
                    (c->p.n + FD_ZC - 1) / FD_ZC);
@@ -370,8 +375,8 @@ hipError_t queue_record(lbm_ctx* c, int64_t step) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   double* slot = ring_buf(c) + (c->ring_head % kRingCap) * NREC;
-  hipLaunchKernelGGL(lbm_final_kernel, dim3(1), dim3(256), 0, c->stream, sp_buf(c), c->sz.nsp,
-                     fp_buf(c), c->sz.nfp, slot, step);
+  hipLaunchKernelGGL(lbm_final_kernel, dim3(1), dim3(256), 0, c->stream, sp_buf(c),
+                     learned ? c->sz.nsp_learned : c->sz.nsp, fp_buf(c), c->sz.nfp, slot, step);
   e = hipGetLastError();
   if (e == hipSuccess) c->ring_head++;
   return e;
@@ -467,6 +472,7 @@ int lbm_init_tgv(const lbm_params* p, void* pop_dev, size_t pop_bytes, void* wor
   c->step = 0;
   c->odd = 0;
   c->ring_head = c->ring_tail = 0;
+  c->mlp = nullptr;
   c->err[0] = 0;
   hipError_t e = by_storage(p->storage, [&](auto* tag) {
     using T = std::remove_pointer_t<decltype(tag)>;
@@ -509,10 +515,13 @@ int lbm_step(lbm_ctx* c, int64_t nsteps) {
       mode = c->odd ? MODE_ODD : MODE_EVEN;
       src = dst = c->pop;
     }
-    hipError_t e = launch_node(c, mode, flags, src, dst, fields_buf(c), sp_buf(c));
+    hipError_t e = c->mlp
+        ? launch_learned_step(c->p.forcing, mode, flags, c->p.n, c->stream, (float*)src, (float*)dst,
+                              c->geo, c->c, fields_buf(c), sp_buf(c), c->mlp)
+        : launch_node(c, mode, flags, src, dst, fields_buf(c), sp_buf(c));
     if (e != hipSuccess) return hip_fail(c, e, "step kernel");
     if (diag) {
-      e = queue_record(c, c->step);
+      e = queue_record(c, c->step, c->mlp != nullptr);
       if (e != hipSuccess) return hip_fail(c, e, "diagnostic kernels");
     }
     c->step++;
@@ -531,7 +540,7 @@ int lbm_sample(lbm_ctx* c) {
   char* src = current_array(c);
   hipError_t e = launch_node(c, mode, K_FIELDS | K_PARTIALS, src, src, fields_buf(c), sp_buf(c));
   if (e != hipSuccess) return hip_fail(c, e, "moments kernel");
-  e = queue_record(c, c->step);
+  e = queue_record(c, c->step, false);
   if (e != hipSuccess) return hip_fail(c, e, "diagnostic kernels");
   return LBM_OK;
 }
@@ -657,6 +666,112 @@ int lbm_bw_probe(int32_t kind, void* dst, const void* src, size_t bytes, void* h
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(nullptr, e, "bandwidth probe");
+  return LBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// learned correction
+// ---------------------------------------------------------------------------
+size_t lbm_mlp_packed_bytes(void) { return sizeof(mlp::Packed); }
+
+int lbm_mlp_pack(const float* params, const float* norm, void* packed, void* stream) {
+  if (!params || !norm || !packed) { set_err(g_err, "NULL buffer"); return LBM_EINVAL; }
+  if ((uintptr_t)packed % 16) { set_err(g_err, "packed buffer must be 16-byte aligned"); return LBM_EINVAL; }
+  hipError_t e = mlp_launch_pack(params, norm, packed, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "pack kernel");
+  return LBM_OK;
+}
+
+int lbm_mlp_forward(const void* packed, const float* x, int64_t rows, float* y, void* stream) {
+  if (!packed || !x || !y || rows < 0) { set_err(g_err, "invalid argument"); return LBM_EINVAL; }
+  if (rows == 0) return LBM_OK;
+  if ((rows + 63) / 64 > 0x7fffffff) { set_err(g_err, "too many rows"); return LBM_EINVAL; }
+  hipError_t e = mlp_launch_forward(packed, x, rows, y, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "forward kernel");
+  return LBM_OK;
+}
+
+size_t lbm_mlp_grad_work_bytes(int64_t batch) {
+  const int64_t blocks = batch > 0 ? (batch + 63) / 64 : 0;
+  return align_up((size_t)blocks * mlp::N_PARAMS * sizeof(float), kAlign) +
+         align_up((size_t)blocks * sizeof(double), kAlign);
+}
+
+int lbm_mlp_grad(const void* packed, const float* x, const float* y, const int64_t* idx, int64_t batch,
+                 float* grad, double* loss, void* work, size_t work_bytes, void* stream) {
+  if (!packed || !x || !y || !idx || !grad || !work || batch <= 0) {
+    set_err(g_err, "invalid argument"); return LBM_EINVAL;
+  }
+  if (work_bytes < lbm_mlp_grad_work_bytes(batch)) {
+    set_err(g_err, "work buffer has %zu bytes, needs %zu", work_bytes, lbm_mlp_grad_work_bytes(batch));
+    return LBM_ESIZE;
+  }
+  const int64_t blocks = (batch + 63) / 64;
+  float* gpart = (float*)work;
+  double* lpart = (double*)((char*)work + align_up((size_t)blocks * mlp::N_PARAMS * sizeof(float), kAlign));
+  hipError_t e = mlp_launch_grad(packed, x, y, idx, batch, gpart, lpart, grad, loss, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "gradient kernels");
+  return LBM_OK;
+}
+
+int lbm_mlp_adam(float* params, float* m, float* v, const float* grad, int64_t t, double lr, void* stream) {
+  if (!params || !m || !v || !grad || t < 1 || !(lr > 0.0)) { set_err(g_err, "invalid argument"); return LBM_EINVAL; }
+  const double b1 = 0.9, b2 = 0.999;
+  const double c1 = 1.0 / (1.0 - std::pow(b1, (double)t)), c2 = 1.0 / (1.0 - std::pow(b2, (double)t));
+  // 1 - beta and the bias corrections in double: 1 - 0.999f in FP32 is off by 1.3e-5
+  hipError_t e = mlp_launch_adam(params, m, v, grad, (float)lr, (float)b1, (float)b2, (float)(1.0 - b1),
+                                 (float)(1.0 - b2), 1e-8f, (float)c1, (float)c2, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "adam kernel");
+  return LBM_OK;
+}
+
+static constexpr int kNormBlocks = 256;
+size_t lbm_mlp_norm_work_bytes(void) { return (size_t)kNormBlocks * (2 * mlp::N_IN + mlp::N_OUT) * sizeof(double); }
+
+int lbm_mlp_norm(const float* x, const float* y, int64_t rows, float* norm, void* work, size_t work_bytes,
+                 void* stream) {
+  if (!x || !y || !norm || !work || rows <= 0) { set_err(g_err, "invalid argument"); return LBM_EINVAL; }
+  if (work_bytes < lbm_mlp_norm_work_bytes()) { set_err(g_err, "work buffer too small"); return LBM_ESIZE; }
+  hipError_t e = mlp_launch_norm(x, y, rows, (double*)work, kNormBlocks, norm, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "normalisation kernels");
+  return LBM_OK;
+}
+
+int lbm_restrict(lbm_ctx* fine, const lbm_ctx* coarse, float* out) {
+  if (!fine || !coarse || !out) { set_err(g_err, "invalid argument"); return LBM_EINVAL; }
+  if (fine->p.q_f != 27 || fine->p.q_g != 19 || coarse->p.q_f != 27 || coarse->p.q_g != 19) {
+    set_err(fine->err, "restriction is defined for D3Q27 x D3Q19"); return LBM_EINVAL;
+  }
+  if (fine->p.n != 4 * coarse->p.n) {
+    set_err(fine->err, "fine n = %d must be 4 x coarse n = %d", fine->p.n, coarse->p.n); return LBM_EINVAL;
+  }
+  const float sf = (float)(4.0 * coarse->d.tau_f / fine->d.tau_f);
+  const float sg = (float)(4.0 * coarse->d.tau_g / fine->d.tau_g);
+  hipError_t e = mlp_launch_restrict(fine->p.storage, current_array(fine), current_mode(fine), fine->geo,
+                                     fine->c, coarse->p.n, sf, sg, out, fine->stream);
+  if (e != hipSuccess) return hip_fail(fine, e, "restriction kernel");
+  return LBM_OK;
+}
+
+int lbm_training_pairs(lbm_ctx* c, const float* a, const float* b, const float* cc, float* x, float* y) {
+  if (!c || !a || !b || !cc || !x || !y) { set_err(g_err, "invalid argument"); return LBM_EINVAL; }
+  if (c->p.q_f != 27 || c->p.q_g != 19) { set_err(c->err, "training pairs need D3Q27 x D3Q19"); return LBM_EINVAL; }
+  hipError_t e = mlp_launch_pairs(c->p.forcing, a, b, cc, c->p.n, c->c, x, y, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "training-pair kernel");
+  return LBM_OK;
+}
+
+int lbm_set_mlp(lbm_ctx* c, const void* packed) {
+  if (!c) { set_err(g_err, "ctx is NULL"); return LBM_EINVAL; }
+  if (packed) {
+    if (c->p.q_f != 27 || c->p.q_g != 19 || c->p.storage != LBM_FP32 || c->p.compute != LBM_COMPUTE_FP32 ||
+        c->p.n % 64 != 0) {
+      set_err(c->err, "the learned step needs D3Q27 x D3Q19, FP32 storage and arithmetic, n %% 64 == 0");
+      return LBM_EINVAL;
+    }
+    if ((uintptr_t)packed % 16) { set_err(c->err, "packed network must be 16-byte aligned"); return LBM_EINVAL; }
+  }
+  c->mlp = packed;
   return LBM_OK;
 }
 

@@ -73,6 +73,17 @@ def _load():
         "lbm_load_populations": (ctypes.c_int, [vp, vp, i64]),
         "lbm_stencil_info": (ctypes.c_int, [i32, P(i32), P(dbl), P(dbl)]),
         "lbm_bw_probe": (ctypes.c_int, [i32, vp, vp, sz, vp]),
+        "lbm_mlp_packed_bytes": (sz, []),
+        "lbm_mlp_pack": (ctypes.c_int, [vp, vp, vp, vp]),
+        "lbm_mlp_forward": (ctypes.c_int, [vp, vp, i64, vp, vp]),
+        "lbm_mlp_grad_work_bytes": (sz, [i64]),
+        "lbm_mlp_grad": (ctypes.c_int, [vp, vp, vp, vp, i64, vp, vp, vp, sz, vp]),
+        "lbm_mlp_adam": (ctypes.c_int, [vp, vp, vp, vp, i64, dbl, vp]),
+        "lbm_mlp_norm_work_bytes": (sz, []),
+        "lbm_mlp_norm": (ctypes.c_int, [vp, vp, i64, vp, vp, sz, vp]),
+        "lbm_restrict": (ctypes.c_int, [vp, vp, vp]),
+        "lbm_training_pairs": (ctypes.c_int, [vp, vp, vp, vp, vp, vp]),
+        "lbm_set_mlp": (ctypes.c_int, [vp, vp]),
         "lbm_get_step": (i64, [vp]),
         "lbm_last_error": (ctypes.c_char_p, [vp]),
         "lbm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -88,7 +99,11 @@ LIB = _load()
 EXPORTED = ("lbm_query_sizes", "lbm_derived", "lbm_init_tgv", "lbm_step", "lbm_sample",
             "lbm_diagnostics", "lbm_read_fields", "lbm_read_populations", "lbm_load_populations",
             "lbm_stencil_info", "lbm_bw_probe", "lbm_get_step", "lbm_last_error",
-            "lbm_status_string", "lbm_destroy")
+            "lbm_status_string", "lbm_destroy", "lbm_mlp_packed_bytes", "lbm_mlp_pack",
+            "lbm_mlp_forward", "lbm_mlp_grad_work_bytes", "lbm_mlp_grad", "lbm_mlp_adam",
+            "lbm_mlp_norm_work_bytes", "lbm_mlp_norm", "lbm_restrict", "lbm_training_pairs",
+            "lbm_set_mlp")
+MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS, MLP_NORM = 47, 64, 41, 9897, 135
 
 
 def _status_name(s):
@@ -177,6 +192,56 @@ def lbm_bw_probe(kind, dst, src, nbytes, stream):
                             nbytes, ctypes.c_void_p(stream)))
 
 
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def lbm_mlp_packed_bytes():
+    return LIB.lbm_mlp_packed_bytes()
+
+
+def lbm_mlp_pack(params, norm, packed, stream):
+    _check(LIB.lbm_mlp_pack(_ptr(params), _ptr(norm), _ptr(packed), ctypes.c_void_p(stream)))
+
+
+def lbm_mlp_forward(packed, x, rows, y, stream):
+    _check(LIB.lbm_mlp_forward(_ptr(packed), _ptr(x), rows, _ptr(y), ctypes.c_void_p(stream)))
+
+
+def lbm_mlp_grad_work_bytes(batch):
+    return LIB.lbm_mlp_grad_work_bytes(batch)
+
+
+def lbm_mlp_grad(packed, x, y, idx, batch, grad, loss, work, stream):
+    _check(LIB.lbm_mlp_grad(_ptr(packed), _ptr(x), _ptr(y), _ptr(idx), batch, _ptr(grad), _ptr(loss),
+                            _ptr(work), work.numel() * work.element_size(), ctypes.c_void_p(stream)))
+
+
+def lbm_mlp_adam(params, m, v, grad, t, lr, stream):
+    _check(LIB.lbm_mlp_adam(_ptr(params), _ptr(m), _ptr(v), _ptr(grad), t, lr, ctypes.c_void_p(stream)))
+
+
+def lbm_mlp_norm_work_bytes():
+    return LIB.lbm_mlp_norm_work_bytes()
+
+
+def lbm_mlp_norm(x, y, rows, norm, work, stream):
+    _check(LIB.lbm_mlp_norm(_ptr(x), _ptr(y), rows, _ptr(norm), _ptr(work),
+                            work.numel() * work.element_size(), ctypes.c_void_p(stream)))
+
+
+def lbm_restrict(fine_ctx, coarse_ctx, out):
+    _check(LIB.lbm_restrict(fine_ctx, coarse_ctx, _ptr(out)), fine_ctx)
+
+
+def lbm_training_pairs(ctx, a, b, c, x, y):
+    _check(LIB.lbm_training_pairs(ctx, _ptr(a), _ptr(b), _ptr(c), _ptr(x), _ptr(y)), ctx)
+
+
+def lbm_set_mlp(ctx, packed):
+    _check(LIB.lbm_set_mlp(ctx, _ptr(packed)), ctx)
+
+
 def lbm_get_step(ctx):
     return LIB.lbm_get_step(ctx)
 
@@ -224,6 +289,17 @@ class Simulation:
         pops = pops.to(device=self.device, dtype=torch.float32).contiguous()
         assert pops.shape == (self.q, self.n, self.n, self.n)
         lbm_load_populations(self.ctx, pops, step)
+
+    def set_mlp(self, packed):
+        """Attach a packed network (a uint8 device tensor kept alive by the caller), or None."""
+        self._mlp = packed
+        lbm_set_mlp(self.ctx, packed)
+
+    def restrict_to(self, coarse):
+        """This (fine) state restricted to the grid of `coarse` (a Simulation), FP32 deviations."""
+        out = torch.empty((coarse.q, coarse.n, coarse.n, coarse.n), dtype=torch.float32, device=self.device)
+        lbm_restrict(self.ctx, coarse.ctx, out)
+        return out
 
     @property
     def step_count(self):

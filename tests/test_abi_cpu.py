@@ -17,7 +17,7 @@ HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))
 
 def test_library_exports_every_declared_entry_point():
     text = open(HEADER).read()
-    declared = set(re.findall(r"^\s*(?:int|int64_t|void|const char\*)\s+(lbm_\w+)\s*\(", text, re.M))
+    declared = set(re.findall(r"^\s*(?:int|int64_t|size_t|void|const char\*)\s+(lbm_\w+)\s*\(", text, re.M))
     assert declared, "no declarations parsed"
     assert declared == set(stgv.EXPORTED)
     for name in declared:

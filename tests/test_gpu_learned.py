@@ -1,0 +1,223 @@
+"""GPU parity of the learned-correction kernels (through the C ABI) against the FP64 oracle.
+
+The network runs on BF16 MFMA with FP32 accumulation: its operands carry a relative
+rounding of 2^-9, so outputs and gradients are compared with ~2-4 % relative tolerances on
+their norms; everything else (packing, normalisation, Adam, restriction, training pairs)
+is FP32 arithmetic on the same inputs and is compared at FP32 rounding level.
+"""
+import numpy as np
+import pytest
+
+from inputs import uniform_deviations
+from oracle import lattice as lat, learned as L, model
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+stgv = pytest.importorskip("paper_2605_14505_amd.stgv")
+
+DEV = "cuda:0"
+
+
+def stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def t32(a):
+    return torch.tensor(np.asarray(a, dtype=np.float32), device=DEV)
+
+
+def packed_net(theta, norm):
+    params = t32(theta)
+    nrm = t32(np.concatenate([np.asarray(v, dtype=np.float64) for v in norm]))
+    packed = torch.empty(stgv.lbm_mlp_packed_bytes(), dtype=torch.uint8, device=DEV)
+    stgv.lbm_mlp_pack(params, nrm, packed, stream())
+    return packed
+
+
+def rel_norm(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def random_norm(rng):
+    return (0.1 * rng.standard_normal(47), 1.0 + 0.2 * rng.uniform(-1, 1, 47),
+            1e-3 * (1.0 + rng.uniform(0, 1, 41)))
+
+
+@pytest.mark.parametrize("rows", [1, 64, 150])
+def test_forward_matches_oracle(rows):
+    rng = np.random.default_rng(rows)
+    theta = L.init_params(1) + 0.01 * rng.standard_normal(L.N_PARAMS)
+    norm = random_norm(rng)
+    x = rng.standard_normal((rows, 47)) * 0.5 + norm[0]
+    packed = packed_net(theta, norm)
+    y = torch.empty((rows, 41), dtype=torch.float32, device=DEV)
+    stgv.lbm_mlp_forward(packed, t32(x), rows, y, stream())
+    xf = x.astype(np.float32).astype(np.float64)
+    o, _ = L.forward(theta, (xf - norm[0]) * norm[1])
+    ref = o * norm[2]
+    err = rel_norm(y.cpu().numpy(), ref)
+    print(f"\nforward rows={rows}: relative error {err:.3e}")
+    assert err < 0.02
+
+
+def test_gradient_and_loss_match_oracle():
+    rng = np.random.default_rng(5)
+    theta = L.init_params(2) + 0.01 * rng.standard_normal(L.N_PARAMS)
+    norm = random_norm(rng)
+    n = 300
+    x = rng.standard_normal((n, 47)) * 0.7 + norm[0]
+    y = rng.standard_normal((n, 41)) * norm[2]
+    idx = rng.permutation(n)[:200]                       # ragged: 200 = 3 blocks + 8
+    packed = packed_net(theta, norm)
+    grad = torch.empty(L.N_PARAMS, dtype=torch.float32, device=DEV)
+    loss = torch.empty(1, dtype=torch.float64, device=DEV)
+    work = torch.empty(stgv.lbm_mlp_grad_work_bytes(200), dtype=torch.uint8, device=DEV)
+    stgv.lbm_mlp_grad(packed, t32(x), t32(y), torch.tensor(idx, dtype=torch.int64, device=DEV), 200,
+                      grad, loss, work, stream())
+    xf = x.astype(np.float32).astype(np.float64)[idx]
+    yf = y.astype(np.float32).astype(np.float64)[idx]
+    ref_loss, ref_g = L.loss_and_grad(theta, (xf - norm[0]) * norm[1], yf / norm[2])
+    g = grad.cpu().numpy()
+    parts = L.unpack(ref_g)
+    got = L.unpack(g.astype(np.float64))
+    for name in parts:
+        e = rel_norm(got[name], parts[name])
+        print(f"grad {name}: relative error {e:.3e}")
+        assert e < 0.05, name
+    assert abs(loss.item() - ref_loss) < 0.02 * ref_loss
+    cos = float(g @ ref_g / (np.linalg.norm(g) * np.linalg.norm(ref_g)))
+    assert cos > 0.999
+
+
+def test_adam_matches_oracle():
+    rng = np.random.default_rng(7)
+    theta = rng.standard_normal(L.N_PARAMS) * 0.1
+    th = t32(theta)
+    m = torch.zeros(L.N_PARAMS, device=DEV)
+    v = torch.zeros(L.N_PARAMS, device=DEV)
+    rt, rm, rv = theta.astype(np.float32).astype(np.float64), np.zeros(L.N_PARAMS), np.zeros(L.N_PARAMS)
+    for t in (1, 2, 3):
+        gr = rng.standard_normal(L.N_PARAMS) * 1e-3
+        stgv.lbm_mlp_adam(th, m, v, t32(gr), t, 1e-3, stream())
+        rt, rm, rv = L.adam_step(rt, gr.astype(np.float32).astype(np.float64), rm, rv, t, 1e-3)
+    np.testing.assert_allclose(th.cpu().numpy(), rt, rtol=1e-6, atol=1e-8)
+    np.testing.assert_allclose(m.cpu().numpy(), rm, rtol=1e-5, atol=1e-10)   # FP32 ulps of |m| ~ 1e-4
+
+
+def test_normalisation_matches_oracle():
+    rng = np.random.default_rng(8)
+    n = 5000
+    x = rng.standard_normal((n, 47)) * rng.uniform(0.1, 3, 47) + rng.uniform(-1, 1, 47)
+    x[:, 0] = 0.25                                        # a constant column
+    y = rng.standard_normal((n, 41)) * 1e-4
+    norm = torch.empty(135, dtype=torch.float32, device=DEV)
+    work = torch.empty(stgv.lbm_mlp_norm_work_bytes(), dtype=torch.uint8, device=DEV)
+    stgv.lbm_mlp_norm(t32(x), t32(y), n, norm, work, stream())
+    ref = L.norm_from_data(x.astype(np.float32), y.astype(np.float32))
+    got = norm.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(got[:47], ref[0], rtol=1e-6, atol=1e-7)
+    assert got[47] == 0.0
+    np.testing.assert_allclose(got[48:94], ref[1][1:], rtol=1e-4)
+    np.testing.assert_allclose(got[94:], ref[2], rtol=1e-6)
+
+
+@pytest.mark.parametrize("forcing", ["guo", "shift"])
+def test_restriction_matches_oracle(forcing):
+    kwf = dict(n=32, forcing=forcing, u0=0.05, re=200.0, fr=0.5, sc=0.7, g_over_n=0.5,
+               noise_amp=1e-4, seed=1)
+    kwc = dict(kwf, n=8)
+    fine = stgv.Simulation(**kwf)
+    coarse = stgv.Simulation(**kwc)
+    fine.step(3)                                          # odd parity: exercises the AA decode
+    got = fine.restrict_to(coarse).cpu().numpy().astype(np.float64)
+    pops = fine.populations().cpu().numpy().astype(np.float64)
+    lf, lg = lat.D3Q27, lat.D3Q19
+    f = pops[:27] + lf.w[:, None, None, None]
+    g = pops[27:] + lg.w[:, None, None, None]
+    pf, pc = model.Params(**kwf), model.Params(**kwc)
+    fc, gc = L.restrict(f, g, pf, pc)
+    ref = np.concatenate([fc - lf.w[:, None, None, None], gc - lg.w[:, None, None, None]])
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(f"\nrestriction {forcing}: relative L-inf {err:.3e}")
+    assert err < 2e-6
+
+
+@pytest.mark.parametrize("forcing", ["guo", "shift"])
+def test_training_pairs_match_oracle(forcing):
+    kw = dict(n=12, forcing=forcing, u0=0.05, re=100.0, fr=0.5, sc=0.7, g_over_n=0.5)
+    sim = stgv.Simulation(**kw)
+    rng_dev = [uniform_deviations(46, 12, 1e-3, seed=s) for s in (11, 12, 13)]
+    a, b, c = (torch.from_numpy(d).to(DEV) for d in rng_dev)
+    x = torch.empty((12 ** 3, 47), dtype=torch.float32, device=DEV)
+    y = torch.empty((12 ** 3, 41), dtype=torch.float32, device=DEV)
+    stgv.lbm_training_pairs(sim.ctx, a, b, c, x, y)
+    torch.cuda.synchronize()
+    lf, lg = lat.D3Q27, lat.D3Q19
+    w = np.concatenate([lf.w, lg.w])[:, None, None, None]
+    A, B, C = (d.astype(np.float64) + w for d in rng_dev)
+    rx, ry = L.pairs_from((A[:27], A[27:]), (B[:27], B[27:]), (C[:27], C[27:]), model.Params(**kw))
+    gx = x.cpu().numpy().T.reshape(47, 12, 12, 12)
+    gy = y.cpu().numpy().T.reshape(41, 12, 12, 12)
+    ex = np.abs(gx - rx).max(axis=(1, 2, 3)) / (np.abs(rx).max(axis=(1, 2, 3)) + 1e-30)
+    ey = np.abs(gy - ry).max() / np.abs(ry).max()
+    print(f"\npairs {forcing}: features max rel {ex.max():.3e}, targets {ey:.3e}")
+    assert ex.max() < 1e-4 and ey < 1e-5
+
+
+def _learned_kw(**over):
+    kw = dict(n=64, forcing="shift", u0=0.05, re=1600.0, fr=0.6, sc=0.7, g_over_n=0.02,
+              noise_amp=1e-6, seed=0)
+    kw.update(over)
+    return kw
+
+
+@pytest.mark.parametrize("forcing", ["guo", "shift"])
+def test_zero_output_layer_is_the_plain_step_bitwise(forcing):
+    kw = _learned_kw(forcing=forcing)
+    theta = L.unpack(L.init_params(3))
+    theta["W3"][:] = 0.0
+    theta["b3"][:] = 0.0
+    packed = packed_net(L.pack(theta), (np.zeros(47), np.ones(47), np.ones(41)))
+    plain = stgv.Simulation(**kw)
+    learned = stgv.Simulation(**kw)
+    learned.set_mlp(packed)
+    for n in (1, 4):                                      # odd and even step counts
+        plain.step(n)
+        learned.step(n)
+        assert torch.equal(plain.populations(), learned.populations())
+
+
+def test_learned_step_matches_oracle():
+    kw = _learned_kw(n=64, forcing="guo", re=800.0)
+    rng = np.random.default_rng(4)
+    theta = L.init_params(4) + 0.01 * rng.standard_normal(L.N_PARAMS)
+    sim = stgv.Simulation(**kw)
+    sim.step(2)
+    pops = sim.populations().cpu().numpy().astype(np.float64)
+    # normalisation from the state's own features, outputs scaled to ~1e-6 corrections
+    lf, lg = lat.D3Q27, lat.D3Q19
+    f0 = pops[:27] + lf.w[:, None, None, None]
+    g0 = pops[27:] + lg.w[:, None, None, None]
+    p = model.Params(**kw)
+    U = model.units(p)
+    xs = L.features(f0, g0, U).reshape(47, -1).T
+    mean, iscale, _ = L.norm_from_data(xs, np.ones((1, 41)))
+    norm = (mean, iscale, np.full(41, 1e-6))
+    packed = packed_net(theta, norm)
+    sim.set_mlp(packed)
+    sim.step(1)
+    got = sim.populations().cpu().numpy().astype(np.float64)
+    fs, gs, _ = L.learned_collide(f0, g0, U, theta, norm)
+    f1, g1 = model.stream(fs, lf), model.stream(gs, lg)
+    ref = np.concatenate([f1 - lf.w[:, None, None, None], g1 - lg.w[:, None, None, None]])
+    fp, gp, _ = model.collide(f0, g0, lf, lg, U)
+    plain = np.concatenate([model.stream(fp, lf) - lf.w[:, None, None, None],
+                            model.stream(gp, lg) - lg.w[:, None, None, None]])
+    corr = ref - plain
+    err_corr = np.abs((got - plain) - corr).max() / np.abs(corr).max()
+    print(f"\nlearned step: correction magnitude {np.abs(corr).max():.3e}, relative error {err_corr:.3e}")
+    assert err_corr < 0.05
+    # the correction leaves mass, momentum and scalar untouched
+    e = lf.e.astype(float)
+    dcorr_f = got[:27] - plain[:27]
+    assert abs(dcorr_f.sum()) < 1e-9 * dcorr_f.size
