@@ -14,6 +14,11 @@ average duration, against the 8 TB/s HBM peak), the streaming-copy ceiling,
 the HBM traffic read from the committed rocprofv3 counter summary when it was
 taken on the current kernel sources, the FP64 oracle timed on the host cores,
 and the energy error of the GPU against the oracle on the 32^3 parity case.
+
+"forms" adds the precision and learned forms: step-kernel throughput of FP16 /
+BF16 weight-shifted storage, of FP64 arithmetic and of the learned 64^3 step,
+and their energy / dissipation histories (E_k, E_p, eps_k, eps_p, -dE/dt) to
+t = 30 against the plain FP32 256^3 run of the same stratified TGV (Fr 0.6).
 """
 import argparse
 import json
@@ -51,7 +56,7 @@ def cpu_baseline(n, steps, forcing):
 
     from oracle import lattice as lat, model
     p = model.Params(n=n, q_f=27, q_g=19, forcing=forcing, u0=0.05, re=1600.0, fr=1.0, sc=0.7,
-                     noise_amp=1e-6, seed=0)
+                     g_over_n=0.02, noise_amp=1e-6, seed=0)
     with threadpool_limits(limits=1):
         U = model.units(p)
         lf, lg = lat.BY_Q[27], lat.BY_Q[19]
@@ -90,6 +95,85 @@ def energy_error(stgv, forcing):
             **{k: float(f"{v:.3e}") for k, v in out.items()}}
 
 
+def kernel_time(stgv, stream, kw, steps, warmup, packed=None):
+    """Average step-kernel time (ms) over `steps` launches, HIP events on the launch stream."""
+    import torch
+    sim = stgv.Simulation(diag_every=0, **kw)
+    if packed is not None:
+        sim.set_mlp(packed)
+    sim.step(warmup)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    sim.step(steps)
+    ev1.record(stream)
+    ev1.synchronize()
+    sim.close()
+    return ev0.elapsed_time(ev1) / steps
+
+
+def history(stgv, kw, t_end, diag_every, packed=None):
+    """Diagnostic records of one run to t_end (convective times L/U)."""
+    import torch
+    from paper_2605_14505_amd import learned
+    steps = int(round(t_end * learned.steps_per_unit_time(kw["n"], kw["u0"])))
+    sim = stgv.Simulation(diag_every=diag_every, **kw)
+    if packed is not None:
+        sim.set_mlp(packed)
+    done = 0
+    while done < steps:
+        k = min(2048, steps - done)
+        sim.step(k)
+        done += k
+    torch.cuda.synchronize()
+    recs = sim.diagnostics(raise_unstable=False)
+    sim.close()
+    return recs
+
+
+def forms(stgv, stream, t_end, steps, warmup):
+    """Precision and learned forms against the plain FP32 256^3 run."""
+    import numpy as np
+    import torch
+    from paper_2605_14505_amd import learned
+    n, nc = 256, 64
+    phys = learned.physics(0.6)
+    base = dict(n=n, q_f=27, q_g=19, **phys)
+    out = {"workload": f"stratified TGV, Re 1600, Fr 0.6, Sc 0.7, velocity shift, G/N 0.02, to t = {t_end}; "
+                       f"errors are relative L2 over the histories against the plain FP32 {n}^3 run"}
+    rates = {}
+    for name, extra, bpn in (("fp32", {}, 368), ("fp16", {"storage": "fp16"}, 184),
+                             ("bf16", {"storage": "bf16"}, 184), ("fp64_arith", {"compute": "fp64"}, 368)):
+        ms = kernel_time(stgv, stream, dict(base, **extra), steps, warmup)
+        rates[name] = {"kernel_ms": round(ms, 5), "mlups": round(n ** 3 / (ms * 1e-3) / 1e6, 1),
+                       "hbm_frac": round(bpn * n ** 3 / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+    net_path = os.path.join(ROOT, "paper_2605_14505_amd", "data", "learned64.npz")
+    if os.path.exists(net_path):
+        z = np.load(net_path, allow_pickle=False)
+        gain = float(z["gain"])
+        net = learned.with_gain(learned.Network(z["theta"], z["norm"]), gain if gain > 0 else 1.0)
+    else:
+        net, gain = learned.Network(seed=0), None       # throughput only: weights do not change it
+    coarse = dict(base, n=nc)
+    for name, packed in (("plain_64", None), ("learned_64", net.packed)):
+        ms = kernel_time(stgv, stream, coarse, 20 * steps // 4, warmup, packed)
+        rates[name] = {"kernel_ms": round(ms, 5), "mlups": round(nc ** 3 / (ms * 1e-3) / 1e6, 1)}
+    out["throughput"] = rates
+    de_c = max(1, int(round(t_end * learned.steps_per_unit_time(nc) / 100)))
+    ref = history(stgv, base, t_end, 4 * de_c)
+    errs = {}
+    for name, extra in (("fp16", {"storage": "fp16"}), ("bf16", {"storage": "bf16"})):
+        errs[name] = learned.series_errors(history(stgv, dict(base, **extra), t_end, 4 * de_c), ref)
+    errs["plain_64"] = learned.series_errors(history(stgv, coarse, t_end, de_c), ref)
+    if gain is not None:
+        errs["learned_64"] = learned.series_errors(
+            history(stgv, coarse, t_end, de_c, net.packed if gain > 0 else None), ref)
+        errs["learned_64"]["gain"] = gain
+    keep = ("finite", "ek", "ep", "eps_k", "eps_p", "eps", "dEdt", "dEdt_peak", "dEdt_peak_ref")
+    out["errors"] = {k: {q: (round(v[q], 6) if isinstance(v[q], float) else v[q]) for q in keep + ("gain",)
+                         if q in v} for k, v in errs.items()}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,9 +187,12 @@ def main():
     ap.add_argument("--compute", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--diag-every", type=int, default=16)
     ap.add_argument("--cpu-sample-n", type=int, default=128)
-    ap.add_argument("--cpu-sample-steps", type=int, default=4)
+    ap.add_argument("--cpu-sample-steps", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-energy-error", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--forms-t", type=float, default=30.0,
+                    help="convective time of the precision / learned form histories")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -122,7 +209,7 @@ def main():
     bpe = 4 if args.storage == "fp32" else 2
     bytes_per_node = 2 * (args.q_f + args.q_g) * bpe
     common = dict(n=n, q_f=args.q_f, q_g=args.q_g, forcing=args.forcing, storage=args.storage,
-                  compute=args.compute, u0=0.05, re=1600.0, fr=1.0, sc=0.7, g_over_n=1.0,
+                  compute=args.compute, u0=0.05, re=1600.0, fr=1.0, sc=0.7, g_over_n=0.02,
                   noise_amp=1e-6, seed=0)
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
@@ -193,7 +280,7 @@ def main():
                         f"{'velocity-shift' if args.forcing == 'shift' else 'Guo source-term'} buoyancy, "
                         f"{args.storage} populations (AA in place), {args.compute} arithmetic, "
                         f"diagnostics every {args.diag_every} steps",
-            "n": n, "q_f": args.q_f, "q_g": args.q_g, "re": 1600, "fr": 1.0, "sc": 0.7, "u0": 0.05,
+            "n": n, "q_f": args.q_f, "q_g": args.q_g, "re": 1600, "fr": 1.0, "sc": 0.7, "u0": 0.05, "g_over_n": 0.02,
             "storage": args.storage, "compute": args.compute, "diag_every": args.diag_every,
             "finite": finite,
         },
@@ -218,6 +305,8 @@ def main():
         out["cpu_baseline"]["host_threads_available"] = os.cpu_count()
     if not args.no_energy_error:
         out["energy_error"] = energy_error(stgv, args.forcing)
+    if not args.no_forms:
+        out["forms"] = forms(stgv, stream, args.forms_t, K, W)
     print(json.dumps(out), flush=True)
 
 
