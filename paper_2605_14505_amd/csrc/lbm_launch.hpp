@@ -22,6 +22,9 @@ inline LaunchShape node_shape(int n) {
   if (n <= 64 && 64 % n == 0) {
     bx = n;
     by = 256 / n;
+  } else if (n % 64 != 0 && n % 32 == 0) {
+    bx = 32;                      // whole 128-byte lines per row, no idle lanes (n = 96, 160, ...)
+    by = 8;
   } else {
     bx = ((n + 63) / 64) * 64;
     if (bx > STGV_BLOCK_X) bx = STGV_BLOCK_X;

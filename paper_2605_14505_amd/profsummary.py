@@ -23,13 +23,17 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PROFILES = os.path.join(ROOT, "profiles")
 
 
+# the sources the FP32 step kernel is compiled from (the profiled kernel)
+STEP_SOURCES = ("stencil.hpp", "lbm_device.hpp", "mlp_device.hpp", "lbm_kernels.hpp", "lbm_launch.hpp",
+                "lbm_instances.hpp", "lbm_fp32.hip")
+
+
 def kernel_source_hash():
     csrc = os.path.join(ROOT, "paper_2605_14505_amd", "csrc")
     h = hashlib.sha256()
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp")):
-            h.update(f.encode())
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in STEP_SOURCES:
+        h.update(f.encode())
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 

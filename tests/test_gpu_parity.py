@@ -170,6 +170,15 @@ def test_reduced_precision_storage_parity(storage, forcing):
 @pytest.mark.parametrize("forcing", ["guo", "shift"])
 @pytest.mark.parametrize("q_f,q_g", [(27, 19), (19, 7)])
 def test_random_state_steps_population_parity(n, forcing, q_f, q_g):
+    _random_state_parity(n, forcing, q_f, q_g)
+
+
+def test_random_state_parity_with_32x8_blocks():
+    # n = 96 (a multiple of 32, not of 64) runs 32 x 8 node blocks
+    _random_state_parity(96, "shift", 27, 19)
+
+
+def _random_state_parity(n, forcing, q_f, q_g):
     kw = dict(n=n, q_f=q_f, q_g=q_g, forcing=forcing, u0=0.05, re=50.0, fr=0.5, sc=0.7,
               g_over_n=1.0)
     sim = gpu_sim(**kw)
