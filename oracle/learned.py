@@ -86,7 +86,7 @@ def features(f, g, U: model.Units):
     lf, lg = lat.D3Q27, lat.D3Q19
     m = model.macro(f, g, lf, lg, U)
     feq = model.f_equilibrium(lf, m.rho, m.ueq)
-    geq = (m.rho_p + model.RHO0) * model.theta(lg, m.ueq)
+    geq = (m.rho_p + model.RHO0) * model.theta(lg, m.utheta)
     mf = np.tensordot(moment_matrix(27).astype(np.float64), f - feq, axes=(1, 0))
     mg = np.tensordot(moment_matrix(19).astype(np.float64), g - geq, axes=(1, 0))
     mf[0] = 0.0

@@ -5,7 +5,8 @@ paper's Section 2 (Eqs. (5)-(18)) one node and one direction at a time, with no
 NumPy broadcasting, so that the vectorised oracle in ``model.py`` can be checked
 against a second, independently written form on tiny boxes.  The readings are
 the same as in ``model.py`` (Shan-Chen shift tau F / rho, Guo second-order
-source term, Chai-Zhao placement of the scalar source, bare u_z in S_i).
+source term, EDM and He-Shan-Doolen forcing, Chai-Zhao placement of the scalar
+source, bare u_z in S_i).
 """
 from . import lattice as lat
 
@@ -27,30 +28,43 @@ def _node_update(fn, gn, lf, lg, tau_f, tau_g, G, beta, forcing):
     rho_p = sig + 0.5 * s - 1.0
     Fz = -G * rho_p
     ux, uy, uz = upx, upy, upz + 0.5 * Fz / rho
-    if forcing == "guo":
+    if forcing in ("guo", "hcz"):
         vx, vy, vz = ux, uy, uz
+    elif forcing == "edm":
+        vx, vy, vz = upx, upy, upz
     else:
         vx, vy, vz = upx, upy, upz + tau_f * Fz / rho
+    # scalar equilibrium velocity: the shifted one for Shan-Chen, the fluid velocity otherwise
+    tx, ty, tz = (vx, vy, vz) if forcing == "shift" else (ux, uy, uz)
     c2 = lf.cs2
+
+    def feq_at(i, ax, ay, az):
+        ex, ey, ez = (float(c) for c in lf.e[i])
+        eu = ex * ax + ey * ay + ez * az
+        uu = ax * ax + ay * ay + az * az
+        return lf.w[i] * rho * (1.0 + eu / c2 + eu * eu / (2.0 * c2 * c2) - uu / (2.0 * c2))
+
     out_f = []
     for i in range(q_f):
         ex, ey, ez = (float(c) for c in lf.e[i])
-        eu = ex * vx + ey * vy + ez * vz
-        uu = vx * vx + vy * vy + vz * vz
-        feq = lf.w[i] * rho * (1.0 + eu / c2 + eu * eu / (2.0 * c2 * c2) - uu / (2.0 * c2))
+        feq = feq_at(i, vx, vy, vz)
         val = fn[i] - (fn[i] - feq) / tau_f
         if forcing == "guo":
             eF = ez * Fz
             euP = ex * ux + ey * uy + ez * uz
             uF = uz * Fz
             val += (1.0 - 0.5 / tau_f) * lf.w[i] * ((eF - uF) / c2 + euP * eF / (c2 * c2))
+        elif forcing == "edm":
+            val += feq_at(i, upx, upy, upz + Fz / rho) - feq
+        elif forcing == "hcz":
+            val += (1.0 - 0.5 / tau_f) * (ez - uz) * Fz / (rho * c2) * feq
         out_f.append(val)
     d2 = lg.cs2
     out_g = []
     for j in range(q_g):
         ex, ey, ez = (float(c) for c in lg.e[j])
-        eu = ex * vx + ey * vy + ez * vz
-        uu = vx * vx + vy * vy + vz * vz
+        eu = ex * tx + ey * ty + ez * tz
+        uu = tx * tx + ty * ty + tz * tz
         th = lg.w[j] * (1.0 + eu / d2 + eu * eu / (2.0 * d2 * d2) - uu / (2.0 * d2))
         geq = (rho_p + 1.0) * th
         out_g.append(gn[j] - (gn[j] - geq) / tau_g + (1.0 - 0.5 / tau_g) * lg.w[j] * s)

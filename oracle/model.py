@@ -8,7 +8,10 @@ against the paper's Section 2:
 * momentum lattice: LBE Eq. (5), moments Eqs. (6)-(7), BGK Eq. (8) with
   tau_f = nu/c_s^2 + 1/2, equilibrium Eq. (9);
 * forcing: the Guo et al. discrete source term (cited with Eq. (5), formula not
-  printed in the paper) or the Shan-Chen velocity shift Eq. (10);
+  printed in the paper) or the Shan-Chen velocity shift Eq. (10); and the two other
+  schemes of the forcing comparison (Section 4), cited there without formulas: the
+  exact difference method (EDM) of Kupershtokh and the He-Shan-Doolen ("HCZ")
+  source term;
 * scalar lattice: LBE Eq. (11) with the stratification source Eqs. (12)-(13),
   BGK Eq. (14), equilibrium Eq. (15) and the corrected zeroth moment
   Eqs. (16)-(17);
@@ -25,6 +28,11 @@ listed in the design notes):
   (``shift_half=True`` selects the printed form, for the record).
 * Guo source term: F_i = (1 - 1/(2 tau)) w_i [(e_i - u)/c_s^2
   + (e_i.u) e_i/c_s^4] . F with u the half-force-corrected velocity of Eq. (7).
+* EDM: relaxation toward f^eq(rho, u') at the bare velocity u' = sum(e f)/rho, plus the
+  equilibrium difference f^eq(rho, u' + F/rho) - f^eq(rho, u'); the fluid velocity is
+  u of Eq. (7), which the scalar equilibrium also uses.
+* HCZ: relaxation toward f^eq(rho, u), u of Eq. (7), plus
+  (1 - 1/(2 tau)) (e_i - u).F / (rho c_s^2) f_i^eq(rho, u); the scalar equilibrium uses u.
 * Scalar source: the LBE adds (1 - 1/(2 tau_g)) S_i and the zeroth moment adds
   S/2 (the Chai-Zhao form the paper cites for Eqs. (16)-(17)); the printed
   placement of R_i and S_i is kept as ``source_as_printed=True`` for the record.
@@ -58,7 +66,7 @@ class Params:
     n: int
     q_f: int = 27
     q_g: int = 19
-    forcing: str = "guo"          # "guo" (source term) | "shift" (Shan-Chen)
+    forcing: str = "guo"          # "guo" | "shift" (Shan-Chen) | "edm" | "hcz"
     u0: float = 0.05              # lattice velocity of the TGV amplitude U
     re: float = 1600.0
     fr: float = 1.0               # math.inf -> no stratification, G = 0
@@ -140,7 +148,8 @@ class Macro:
     rho_p: np.ndarray     # rho', Eq. (16)
     F: np.ndarray         # (3, ...), Eq. (18)
     u: np.ndarray         # physical velocity, Eq. (7)
-    ueq: np.ndarray       # velocity fed to the equilibria
+    ueq: np.ndarray       # velocity of the momentum equilibrium the collision relaxes to
+    utheta: np.ndarray    # velocity of the scalar equilibrium, Eq. (15)
 
 
 def macro(f, g, lf, lg, U: Units) -> Macro:
@@ -155,14 +164,17 @@ def macro(f, g, lf, lg, U: Units) -> Macro:
     F = np.zeros_like(up)
     F[2] = -U.G * rho_p                                            # Eq. (18)
     u = up + F / (2.0 * rho)                                       # Eq. (7)
-    if U.forcing == "guo":
+    if U.forcing in ("guo", "hcz"):
         ueq = u
     elif U.forcing == "shift":
         k = 0.5 if U.shift_half else 1.0
         ueq = up + k * U.tau_f * F / rho                           # Eq. (10)
+    elif U.forcing == "edm":
+        ueq = up
     else:
         raise ValueError(U.forcing)
-    return Macro(rho, up, sigma, s, rho_p, F, u, ueq)
+    utheta = ueq if U.forcing == "shift" else u
+    return Macro(rho, up, sigma, s, rho_p, F, u, ueq, utheta)
 
 
 def guo_source(L, tau, u, F):
@@ -173,6 +185,19 @@ def guo_source(L, tau, u, F):
     uF = (u * F).sum(0)
     w = L.w.reshape((-1,) + (1,) * (u.ndim - 1))
     return (1.0 - 1.0 / (2.0 * tau)) * w * ((eF - uF) / L.cs2 + eu * eF / L.cs2 ** 2)
+
+
+def hcz_source(L, tau, rho, u, F, feq):
+    """He-Shan-Doolen force term (1 - 1/(2 tau)) (e_i - u).F / (rho c_s^2) f_i^eq."""
+    e = L.e.astype(np.float64)
+    eF = np.tensordot(e, F, axes=(1, 0))
+    uF = (u * F).sum(0)
+    return (1.0 - 1.0 / (2.0 * tau)) * (eF - uF) / (rho * L.cs2) * feq
+
+
+def edm_source(L, rho, up, F):
+    """Kupershtokh's exact difference f^eq(rho, u' + F/rho) - f^eq(rho, u')."""
+    return f_equilibrium(L, rho, up + F / rho) - f_equilibrium(L, rho, up)
 
 
 # ----------------------------------------------------------------------------
@@ -186,7 +211,11 @@ def collide(f, g, lf, lg, U: Units, m: Macro = None):
     fs = f - (f - feq) / U.tau_f                                   # Eq. (8)
     if U.forcing == "guo":
         fs = fs + guo_source(lf, U.tau_f, m.u, m.F)
-    geq = (m.rho_p + RHO0) * theta(lg, m.ueq)                      # Eq. (15)
+    elif U.forcing == "edm":
+        fs = fs + edm_source(lf, m.rho, m.up, m.F)
+    elif U.forcing == "hcz":
+        fs = fs + hcz_source(lf, U.tau_f, m.rho, m.u, m.F, feq)
+    geq = (m.rho_p + RHO0) * theta(lg, m.utheta)                   # Eq. (15)
     S = lg.w.reshape((-1,) + (1,) * m.s.ndim) * m.s                # Eq. (12)
     gs = g - (g - geq) / U.tau_g                                   # Eq. (14)
     if U.source_as_printed:

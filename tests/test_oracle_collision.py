@@ -47,8 +47,11 @@ def test_d3q7_theta_keeps_zeroth_and_first_moment():
                                rtol=0, atol=1e-15)
 
 
+FORCINGS = ["guo", "shift", "edm", "hcz"]
+
+
 @pytest.mark.parametrize("q_f,q_g", PAIRS)
-@pytest.mark.parametrize("forcing", ["guo", "shift"])
+@pytest.mark.parametrize("forcing", FORCINGS)
 def test_collision_mass_momentum_budget(q_f, q_g, forcing):
     """A forced BGK collision keeps mass and adds exactly F of momentum per node."""
     lf, lg = lat.BY_Q[q_f], lat.BY_Q[q_g]
@@ -92,7 +95,7 @@ def test_guo_source_moments(q):
 
 
 @pytest.mark.parametrize("q_f,q_g", PAIRS)
-@pytest.mark.parametrize("forcing", ["guo", "shift"])
+@pytest.mark.parametrize("forcing", FORCINGS)
 def test_scalar_budget_gains_exactly_the_source(q_f, q_g, forcing):
     """Under the Chai-Zhao reading sum_j g*_j - sum_j g_j = s at every node (Eqs. (11), (16)-(17))."""
     lf, lg = lat.BY_Q[q_f], lat.BY_Q[q_g]
@@ -136,7 +139,7 @@ def test_streaming_is_a_permutation_with_period_n(q):
 
 
 @pytest.mark.parametrize("q_f,q_g", PAIRS)
-@pytest.mark.parametrize("forcing", ["guo", "shift"])
+@pytest.mark.parametrize("forcing", FORCINGS)
 def test_vectorised_step_matches_node_by_node_transcription(q_f, q_g, forcing):
     lf, lg = lat.BY_Q[q_f], lat.BY_Q[q_g]
     rng = np.random.default_rng(8)
@@ -172,3 +175,72 @@ def test_fp64_storage_is_the_plain_oracle():
     np.testing.assert_array_equal(g1, g2)
     (f3, _), _ = model.run(p, 3, storage="fp16")
     assert 0 < np.abs(f3 - f1).max() < 1e-4
+
+
+@pytest.mark.parametrize("q", [15, 19, 27])
+def test_hcz_source_moments(q):
+    """sum F_i = 0, sum e_i F_i = a F, second moment a [uF + Fu - u u (u.F)/c_s^2], a = 1 - 1/(2 tau):
+    the third equilibrium moment rho c_s^2 (u d + d u + ...) of a lattice with fourth-order isotropy."""
+    L = lat.BY_Q[q]
+    rng = np.random.default_rng(11)
+    u = 0.1 * rng.uniform(-1, 1, (3, 30))
+    F = 1e-3 * rng.uniform(-1, 1, (3, 30))
+    rho = 1.0 + 0.05 * rng.uniform(-1, 1, 30)
+    tau = 0.68
+    feq = model.f_equilibrium(L, rho, u)
+    Fi = model.hcz_source(L, tau, rho, u, F, feq)
+    a = 1.0 - 1.0 / (2.0 * tau)
+    e = L.e.astype(float)
+    np.testing.assert_allclose(Fi.sum(0), 0.0, atol=1e-18)
+    np.testing.assert_allclose(np.tensordot(e.T, Fi, axes=(1, 0)), a * F, rtol=1e-12, atol=1e-19)
+    M2 = np.einsum("ia,ib,in->abn", e, e, Fi)
+    uF = (u * F).sum(0)
+    expect = a * (u[:, None] * F[None, :] + F[:, None] * u[None, :]
+                  - u[:, None] * u[None, :] * uF / L.cs2)
+    np.testing.assert_allclose(M2, expect, rtol=1e-11, atol=1e-18)
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_hcz_and_guo_terms_coincide_at_rest(q):
+    """At u = 0 both discrete force terms are (1 - 1/(2 tau)) w_i e_i.F / c_s^2."""
+    L = lat.BY_Q[q]
+    rng = np.random.default_rng(12)
+    F = 1e-3 * rng.uniform(-1, 1, (3, 10))
+    rho = 1.0 + 0.05 * rng.uniform(-1, 1, 10)
+    u = np.zeros((3, 10))
+    hcz = model.hcz_source(L, 0.6, rho, u, F, model.f_equilibrium(L, rho, u))
+    np.testing.assert_allclose(hcz, model.guo_source(L, 0.6, u, F), rtol=1e-14, atol=1e-20)
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_edm_difference_moments(q):
+    """f^eq(u' + du) - f^eq(u'): zeroth moment 0, first rho du, second rho[(u'+du)(u'+du) - u'u']."""
+    L = lat.BY_Q[q]
+    rng = np.random.default_rng(13)
+    up = 0.1 * rng.uniform(-1, 1, (3, 20))
+    F = 1e-3 * rng.uniform(-1, 1, (3, 20))
+    rho = 1.0 + 0.05 * rng.uniform(-1, 1, 20)
+    d = model.edm_source(L, rho, up, F)
+    du = F / rho
+    e = L.e.astype(float)
+    # difference of two O(1) equilibria: rounding of a few ulps of rho ~ 1
+    np.testing.assert_allclose(d.sum(0), 0.0, atol=1e-15)
+    np.testing.assert_allclose(np.tensordot(e.T, d, axes=(1, 0)), F, rtol=0, atol=1e-15)
+    v = up + du
+    expect = rho * (v[:, None] * v[None, :] - up[:, None] * up[None, :])
+    np.testing.assert_allclose(np.einsum("ia,ib,in->abn", e, e, d), expect, rtol=0, atol=1e-15)
+    assert np.abs(expect).max() > 1e-5
+
+
+def test_edm_agrees_with_the_shan_chen_shift_to_first_order_in_the_force():
+    """EDM expands the Shan-Chen shift exactly; the two collisions differ only at O(F^2)."""
+    lf, lg = lat.D3Q27, lat.D3Q19
+    f, g = _rand_state(np.random.default_rng(14), (50,), lf, lg)
+    diffs = []
+    for nb in (0.04, 0.02):
+        out = [model.collide(f, g, lf, lg, model.raw_units(0.8, 0.6, nb=nb, forcing=k))[0]
+               for k in ("edm", "shift")]
+        diffs.append(np.abs(out[0] - out[1]).max())
+    # F = G rho' with G = (G/N) nb and rho' set by the random scalar populations: halving nb
+    # halves F, so an O(F^2) difference drops 4-fold (an O(F) one would only halve)
+    assert diffs[1] > 0 and 3.6 < diffs[0] / diffs[1] < 4.4

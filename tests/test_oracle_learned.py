@@ -146,7 +146,7 @@ def test_conserved_feature_slots_are_the_full_moments(forcing):
     x = L.features(f, g, U)
     m = model.macro(f, g, lat.D3Q27, lat.D3Q19, U)
     feq = model.f_equilibrium(lat.D3Q27, m.rho, m.ueq)
-    geq = (m.rho_p + model.RHO0) * model.theta(lat.D3Q19, m.ueq)
+    geq = (m.rho_p + model.RHO0) * model.theta(lat.D3Q19, m.utheta)
     e = lat.D3Q27.e.astype(float)
     np.testing.assert_allclose(x[0], (f - feq).sum(0), rtol=0, atol=1e-15)
     np.testing.assert_allclose(x[1:4], np.tensordot(e.T, f - feq, axes=(1, 0)), rtol=0, atol=1e-16)

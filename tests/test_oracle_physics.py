@@ -90,7 +90,8 @@ def _internal_wave(n=32, nb=0.01, tau_f=0.6, tau_g=0.6, forcing="guo", q_f=27, q
     return p[1] / w0
 
 
-@pytest.mark.parametrize("forcing,q_f,q_g", [("guo", 27, 19), ("shift", 27, 19), ("shift", 19, 7)])
+@pytest.mark.parametrize("forcing,q_f,q_g", [("guo", 27, 19), ("shift", 27, 19), ("shift", 19, 7),
+                                             ("edm", 27, 19), ("hcz", 27, 19)])
 def test_internal_wave_frequency(forcing, q_f, q_g):
     r = _internal_wave(forcing=forcing, q_f=q_f, q_g=q_g)
     assert abs(r - 1.0) < 0.01
