@@ -29,6 +29,8 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 PEAK_HBM_GBS = 8000.0
+FORCING_NAMES = {"guo": "Guo source-term", "shift": "velocity-shift", "edm": "exact-difference (EDM)",
+                 "hcz": "He-Shan-Doolen source-term"}
 
 
 def read_traffic(workload_key, n3, bytes_per_node):
@@ -182,7 +184,7 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--q-f", type=int, default=27)
     ap.add_argument("--q-g", type=int, default=19)
-    ap.add_argument("--forcing", default="shift", choices=["guo", "shift"])
+    ap.add_argument("--forcing", default="shift", choices=["guo", "shift", "edm", "hcz"])
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16"])
     ap.add_argument("--compute", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--diag-every", type=int, default=16)
@@ -277,7 +279,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"stratified Taylor-Green vortex, {n}^3 periodic box, D3Q{args.q_f}xD3Q{args.q_g}, "
-                        f"{'velocity-shift' if args.forcing == 'shift' else 'Guo source-term'} buoyancy, "
+                        f"{FORCING_NAMES[args.forcing]} buoyancy, "
                         f"{args.storage} populations (AA in place), {args.compute} arithmetic, "
                         f"diagnostics every {args.diag_every} steps",
             "n": n, "q_f": args.q_f, "q_g": args.q_g, "re": 1600, "fr": 1.0, "sc": 0.7, "u0": 0.05, "g_over_n": 0.02,

@@ -52,8 +52,12 @@ typedef enum {
 } lbm_status;
 
 typedef enum {
-  LBM_FORCE_GUO = 0,  /* Guo-Zheng-Shi discrete source term (cited with Eq. (5)) */
-  LBM_FORCE_SHIFT = 1 /* Shan-Chen velocity shift u_eq = u' + tau_f F / rho (Eq. (10)) */
+  LBM_FORCE_GUO = 0,   /* Guo-Zheng-Shi discrete source term (cited with Eq. (5)) */
+  LBM_FORCE_SHIFT = 1, /* Shan-Chen velocity shift u_eq = u' + tau_f F / rho (Eq. (10)) */
+  LBM_FORCE_EDM = 2,   /* exact difference method (Kupershtokh), compared in Section 4:
+                          relax to f^eq(u'), add f^eq(u' + F/rho) - f^eq(u') */
+  LBM_FORCE_HCZ = 3    /* He-Shan-Doolen source term, compared in Section 4: relax to
+                          f^eq(u), add (1 - 1/2tau)(e - u).F/(rho c_s^2) f^eq(u) */
 } lbm_forcing;
 
 typedef enum {
@@ -216,7 +220,7 @@ int lbm_mlp_norm(const float* x_dev, const float* y_dev, int64_t rows, float* no
 /* Restrict the current state of a fine D3Q27 x D3Q19 context to the grid of a
  * coarse one (fine n = 4 coarse n): separable [1,2,2,2,1]/8 filter sampled at
  * every 4th node, non-conserved filtered non-equilibrium moments rescaled by
- * 4 tau_coarse / tau_fine.  coarse_dev: (q_f + q_g) n_c^3 FP32 deviations in the
+ * 4 tau_coarse / tau_fine (Guo or velocity-shift contexts).  coarse_dev: (q_f + q_g) n_c^3 FP32 deviations in the
  * layout of lbm_read_populations.  Queued on the fine context's stream. */
 int lbm_restrict(lbm_ctx* fine, const lbm_ctx* coarse, float* coarse_dev);
 
@@ -229,7 +233,7 @@ int lbm_training_pairs(lbm_ctx* coarse, const float* a_dev, const float* b_dev, 
                        float* x_dev, float* y_dev);
 
 /* Attach (or, with NULL, detach) a packed network to a D3Q27 x D3Q19 context
- * with FP32 storage and arithmetic and n % 64 == 0; later lbm_step calls run
+ * with Guo or velocity-shift forcing, FP32 storage and arithmetic and n % 64 == 0; later lbm_step calls run
  * the fused learned step.  packed_dev must stay valid while attached. */
 int lbm_set_mlp(lbm_ctx* ctx, const void* packed_dev);
 

@@ -24,7 +24,9 @@
 namespace stgv {
 
 enum Mode : int { MODE_EVEN = 0, MODE_ODD = 1, MODE_AB = 2 };
-enum Forcing : int { FORCE_GUO = 0, FORCE_SHIFT = 1 };
+// Guo source term, Shan-Chen velocity shift (Eq. (10)), exact difference method
+// (Kupershtokh), He-Shan-Doolen source term: the four schemes of the forcing comparison.
+enum Forcing : int { FORCE_GUO = 0, FORCE_SHIFT = 1, FORCE_EDM = 2, FORCE_HCZ = 3 };
 enum KernelFlags : int {
   K_COLLIDE = 1,    // collide and stream (the time step)
   K_FIELDS = 2,     // write rho - 1, u_x, u_y, u_z, rho' per node
@@ -248,7 +250,7 @@ struct NodeMacro {
   C s;          // -u'_z (d rho_b/dz)_LU
   C Fz;         // -G rho'
   C ux, uy, uz; // physical velocity, Eq. (7)
-  C vx, vy, vz; // velocity in the equilibria
+  C vx, vy, vz; // velocity of the momentum equilibrium the collision relaxes to
 };
 
 template <int QF, int QG, int FORCE, typename C>
@@ -270,8 +272,9 @@ __device__ __forceinline__ void node_macro(const C* f, const C* g, const PhysCon
   m.uz = upz + C(0.5) * Fz * inv_rho;         // Eq. (7)
   m.vx = m.ux;
   m.vy = m.uy;
-  if (FORCE == FORCE_GUO) m.vz = m.uz;
-  else m.vz = upz + (C)c.tau_f * Fz * inv_rho;  // Shan-Chen shift, Eq. (10) (tau F / rho)
+  if (FORCE == FORCE_SHIFT) m.vz = upz + (C)c.tau_f * Fz * inv_rho;  // Shan-Chen shift, Eq. (10) (tau F / rho)
+  else if (FORCE == FORCE_EDM) m.vz = upz;                            // EDM relaxes to f^eq(u')
+  else m.vz = m.uz;                                                   // Guo, HCZ: u of Eq. (7)
 }
 
 template <int QF, int QG, int FORCE, typename C>
@@ -282,6 +285,7 @@ struct Collision {
   static constexpr C icg = C(1.0 / SG::cs2);
   const NodeMacro<C>& m;
   C vx, vy, vz, usq, omega_f, omega_g, tau_f, base_f, conc, base_g;
+  C tx, ty, tz;   // velocity of the scalar equilibrium
 
   __device__ __forceinline__ Collision(const PhysConsts& c, const NodeMacro<C>& mm) : m(mm) {
     vx = m.vx; vy = m.vy; vz = m.vz;
@@ -289,7 +293,15 @@ struct Collision {
     omega_f = (C)c.omega_f; omega_g = (C)c.omega_g; tau_f = (C)c.tau_f;
     base_f = m.drho - C(0.5) * icf * m.rho * usq;
     conc = C(1) + m.rho_p;
-    base_g = -C(0.5) * icg * usq;
+    // the scalar equilibrium moves with the velocity of the momentum equilibrium,
+    // except under EDM, whose fluid velocity is u of Eq. (7)
+    if (FORCE == FORCE_EDM) {
+      tx = m.ux; ty = m.uy; tz = m.uz;
+      base_g = -C(0.5) * icg * (tx * tx + ty * ty + tz * tz);
+    } else {
+      tx = vx; ty = vy; tz = vz;
+      base_g = -C(0.5) * icg * usq;
+    }
   }
   // momentum lattice: df_eq = w [drho + rho (xi + xi^2/2 - u^2/(2 c^2))], xi = e.u / c^2
   __device__ __forceinline__ C feq(int i) const {
@@ -298,7 +310,7 @@ struct Collision {
   }
   // scalar lattice: dg_eq = w [rho' + (1 + rho') (xi + xi^2/2 - u^2/(2 c^2))]
   __device__ __forceinline__ C geq(int j) const {
-    const C xi = icg * dot_e(SG::ex[j], SG::ey[j], SG::ez[j], vx, vy, vz);
+    const C xi = icg * dot_e(SG::ex[j], SG::ey[j], SG::ez[j], tx, ty, tz);
     return C(SG::w[j]) * (m.rho_p + conc * (base_g + xi * (C(1) + C(0.5) * xi)));
   }
   // f[i] <- d_i = f_i^eq - f_i and g[j] <- h_j = g_j^eq - g_j
@@ -311,25 +323,37 @@ struct Collision {
   // From the increments to the post-collision populations.
   //   f*_i = f_i + omega (d_i - p_i) + G_i = f_i^eq + [(omega - 1) d_i - omega p_i + G_i]
   // with p_i = w_i (r_0 + e_i . r / c^2) the projection of the moment residual
-  // and G_i the Guo term; the bracket is formed with fused multiply-adds so the
-  // small terms (p_i, G_i ~ 1e-12) shift its single rounding instead of
-  // deciding ties of the final sum: ties broken by a term whose sign follows
-  // e_i . F would bias the node mass a little every step.
+  // and G_i the force term of the scheme; the bracket is formed with fused
+  // multiply-adds so the small terms (p_i, G_i ~ 1e-12) shift its single rounding
+  // instead of deciding ties of the final sum: ties broken by a term whose sign
+  // follows e_i . F would bias the node mass a little every step.
+  //   Guo: G_i = (1 - omega/2) w [(e_z - u_z) / c^2 + (e.u) e_z / c^4] Fz;
+  //   EDM: G_i = f^eq_i(u' + F/rho) - f^eq_i(u'), which for the second-order
+  //        equilibrium is exactly w [(e_z - u_z) / c^2 + (e.u) e_z / c^4] Fz with
+  //        u = u' + F/(2 rho): the Guo bracket without the factor (1 - omega/2);
+  //   HCZ: G_i = (1 - omega/2) (e_z - u_z) Fz / (rho c^2) f^eq_i(u).
+  // The increments carry the momentum rho u_eq - j: F/2 (Guo, HCZ), tau F
+  // (shift), 0 (EDM).
   __device__ __forceinline__ void finish(C* f, C* g) const {
     C r0, rx, ry, rz;
     pair_moments<QF>(f, r0, rx, ry, rz);
-    rz -= (FORCE == FORCE_GUO) ? C(0.5) * m.Fz : tau_f * m.Fz;
-    const C guo_c = (FORCE == FORCE_GUO) ? (C(1) - C(0.5) * omega_f) * m.Fz : C(0);
+    if (FORCE == FORCE_GUO || FORCE == FORCE_HCZ) rz -= C(0.5) * m.Fz;
+    else if (FORCE == FORCE_SHIFT) rz -= tau_f * m.Fz;
+    const C half_c = (C(1) - C(0.5) * omega_f) * m.Fz;
+    const C bracket_c = (FORCE == FORCE_GUO) ? half_c : m.Fz;          // Guo / EDM
+    const C hcz_c = icf * half_c / m.rho;                               // HCZ
 #pragma unroll
     for (int i = 0; i < QF; ++i) {
       const C p = C(SF::w[i]) * (r0 + icf * dot_e(SF::ex[i], SF::ey[i], SF::ez[i], rx, ry, rz));
       C small = -omega_f * p;
-      if (FORCE == FORCE_GUO) {
-        // Guo term with F = (0, 0, Fz): (1 - omega/2) w [(e_z - u_z) / c^2 + (e.u) e_z / c^4] Fz
-        const C eu = dot_e(SF::ex[i], SF::ey[i], SF::ez[i], vx, vy, vz);
+      if (FORCE == FORCE_GUO || FORCE == FORCE_EDM) {
+        const C eu = dot_e(SF::ex[i], SF::ey[i], SF::ez[i], m.ux, m.uy, m.uz);
         C br = -icf * m.uz;
         if (SF::ez[i] != 0) br += SF::ez[i] > 0 ? icf * (C(1) + icf * eu) : -icf * (C(1) + icf * eu);
-        small = fma_c(-omega_f, p, C(SF::w[i]) * guo_c * br);
+        small = fma_c(-omega_f, p, C(SF::w[i]) * bracket_c * br);
+      } else if (FORCE == FORCE_HCZ) {
+        const C ez_u = C(SF::ez[i]) - m.uz;
+        small = fma_c(-omega_f, p, hcz_c * ez_u * (C(SF::w[i]) + feq(i)));
       }
       f[i] = feq(i) + fma_c(omega_f - C(1), f[i], small);
     }

@@ -20,6 +20,21 @@ hipError_t go_step(const LaunchShape& sh, hipStream_t st, T* pop, T* dst, Geomet
   return hipGetLastError();
 }
 
+template <int QF, int QG, int FORCE, typename T>
+hipError_t step_force(int mode, bool diag, const LaunchShape& sh, hipStream_t st, T* pop, T* dst,
+                      Geometry geo, PhysConsts c, float* fields, double* partials) {
+  constexpr int STEP = K_COLLIDE;
+  constexpr int STEP_DIAG = K_COLLIDE | K_FIELDS | K_PARTIALS;
+#define STGV_GO(M) \
+  return diag ? go_step<QF, QG, FORCE, T, M, STEP_DIAG>(sh, st, pop, dst, geo, c, fields, partials) \
+              : go_step<QF, QG, FORCE, T, M, STEP>(sh, st, pop, dst, geo, c, fields, partials)
+  if (mode == MODE_EVEN) STGV_GO(MODE_EVEN);
+  if (mode == MODE_ODD) STGV_GO(MODE_ODD);
+  if (mode == MODE_AB) STGV_GO(MODE_AB);
+#undef STGV_GO
+  return hipErrorInvalidValue;
+}
+
 template <int QF, int QG, typename T>
 hipError_t step_pair(int force, int mode, int flags, const LaunchShape& sh, hipStream_t st, T* pop,
                      T* dst, Geometry geo, PhysConsts c, float* fields, double* partials) {
@@ -27,30 +42,27 @@ hipError_t step_pair(int force, int mode, int flags, const LaunchShape& sh, hipS
   constexpr int STEP_DIAG = K_COLLIDE | K_FIELDS | K_PARTIALS;
   constexpr int SAMPLE = K_FIELDS | K_PARTIALS;
   constexpr int FIELDS = K_FIELDS;
-#define STGV_GO(F, M, FL) return go_step<QF, QG, F, T, M, FL>(sh, st, pop, dst, geo, c, fields, partials)
   if (flags == STEP || flags == STEP_DIAG) {
     const bool d = flags == STEP_DIAG;
-    if (force == FORCE_GUO) {
-      if (mode == MODE_EVEN) { if (d) STGV_GO(FORCE_GUO, MODE_EVEN, STEP_DIAG); STGV_GO(FORCE_GUO, MODE_EVEN, STEP); }
-      if (mode == MODE_ODD) { if (d) STGV_GO(FORCE_GUO, MODE_ODD, STEP_DIAG); STGV_GO(FORCE_GUO, MODE_ODD, STEP); }
-      if (mode == MODE_AB) { if (d) STGV_GO(FORCE_GUO, MODE_AB, STEP_DIAG); STGV_GO(FORCE_GUO, MODE_AB, STEP); }
-    } else if (force == FORCE_SHIFT) {
-      if (mode == MODE_EVEN) { if (d) STGV_GO(FORCE_SHIFT, MODE_EVEN, STEP_DIAG); STGV_GO(FORCE_SHIFT, MODE_EVEN, STEP); }
-      if (mode == MODE_ODD) { if (d) STGV_GO(FORCE_SHIFT, MODE_ODD, STEP_DIAG); STGV_GO(FORCE_SHIFT, MODE_ODD, STEP); }
-      if (mode == MODE_AB) { if (d) STGV_GO(FORCE_SHIFT, MODE_AB, STEP_DIAG); STGV_GO(FORCE_SHIFT, MODE_AB, STEP); }
+    switch (force) {
+      case FORCE_GUO: return step_force<QF, QG, FORCE_GUO, T>(mode, d, sh, st, pop, dst, geo, c, fields, partials);
+      case FORCE_SHIFT: return step_force<QF, QG, FORCE_SHIFT, T>(mode, d, sh, st, pop, dst, geo, c, fields, partials);
+      case FORCE_EDM: return step_force<QF, QG, FORCE_EDM, T>(mode, d, sh, st, pop, dst, geo, c, fields, partials);
+      case FORCE_HCZ: return step_force<QF, QG, FORCE_HCZ, T>(mode, d, sh, st, pop, dst, geo, c, fields, partials);
+      default: return hipErrorInvalidValue;
     }
-    return hipErrorInvalidValue;
   }
   // Moment-only passes read the natural layout (MODE_EVEN, also the AB lattice)
   // or the odd AA layout; the physical velocity does not depend on the forcing.
+#define STGV_GO(M, FL) return go_step<QF, QG, FORCE_GUO, T, M, FL>(sh, st, pop, dst, geo, c, fields, partials)
   const int gm = (mode == MODE_ODD) ? MODE_ODD : MODE_EVEN;
   if (flags == SAMPLE) {
-    if (gm == MODE_EVEN) STGV_GO(FORCE_GUO, MODE_EVEN, SAMPLE);
-    STGV_GO(FORCE_GUO, MODE_ODD, SAMPLE);
+    if (gm == MODE_EVEN) STGV_GO(MODE_EVEN, SAMPLE);
+    STGV_GO(MODE_ODD, SAMPLE);
   }
   if (flags == FIELDS) {
-    if (gm == MODE_EVEN) STGV_GO(FORCE_GUO, MODE_EVEN, FIELDS);
-    STGV_GO(FORCE_GUO, MODE_ODD, FIELDS);
+    if (gm == MODE_EVEN) STGV_GO(MODE_EVEN, FIELDS);
+    STGV_GO(MODE_ODD, FIELDS);
   }
 #undef STGV_GO
   return hipErrorInvalidValue;

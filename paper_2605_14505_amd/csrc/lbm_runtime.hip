@@ -227,7 +227,7 @@ int derive(const lbm_params* p, Derived* d, char* err) {
     set_err(err, "stencil pair D3Q%d x D3Q%d not supported (27x19, 27x7, 19x7)", p->q_f, p->q_g);
     return LBM_EINVAL;
   }
-  if (p->forcing != LBM_FORCE_GUO && p->forcing != LBM_FORCE_SHIFT) {
+  if (p->forcing < LBM_FORCE_GUO || p->forcing > LBM_FORCE_HCZ) {
     set_err(err, "forcing = %d invalid", p->forcing); return LBM_EINVAL;
   }
   if (p->storage < LBM_FP32 || p->storage > LBM_BF16) {
@@ -737,10 +737,17 @@ int lbm_mlp_norm(const float* x, const float* y, int64_t rows, float* norm, void
   return LBM_OK;
 }
 
+static bool learned_forcing(const lbm_ctx* c) {
+  return c->p.forcing == LBM_FORCE_GUO || c->p.forcing == LBM_FORCE_SHIFT;
+}
+
 int lbm_restrict(lbm_ctx* fine, const lbm_ctx* coarse, float* out) {
   if (!fine || !coarse || !out) { set_err(g_err, "invalid argument"); return LBM_EINVAL; }
   if (fine->p.q_f != 27 || fine->p.q_g != 19 || coarse->p.q_f != 27 || coarse->p.q_g != 19) {
     set_err(fine->err, "restriction is defined for D3Q27 x D3Q19"); return LBM_EINVAL;
+  }
+  if (!learned_forcing(fine) || !learned_forcing(coarse)) {
+    set_err(fine->err, "the learned form is defined for Guo and velocity-shift forcing"); return LBM_EINVAL;
   }
   if (fine->p.n != 4 * coarse->p.n) {
     set_err(fine->err, "fine n = %d must be 4 x coarse n = %d", fine->p.n, coarse->p.n); return LBM_EINVAL;
@@ -756,6 +763,9 @@ int lbm_restrict(lbm_ctx* fine, const lbm_ctx* coarse, float* out) {
 int lbm_training_pairs(lbm_ctx* c, const float* a, const float* b, const float* cc, float* x, float* y) {
   if (!c || !a || !b || !cc || !x || !y) { set_err(g_err, "invalid argument"); return LBM_EINVAL; }
   if (c->p.q_f != 27 || c->p.q_g != 19) { set_err(c->err, "training pairs need D3Q27 x D3Q19"); return LBM_EINVAL; }
+  if (!learned_forcing(c)) {
+    set_err(c->err, "the learned form is defined for Guo and velocity-shift forcing"); return LBM_EINVAL;
+  }
   hipError_t e = mlp_launch_pairs(c->p.forcing, a, b, cc, c->p.n, c->c, x, y, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "training-pair kernel");
   return LBM_OK;
@@ -765,8 +775,9 @@ int lbm_set_mlp(lbm_ctx* c, const void* packed) {
   if (!c) { set_err(g_err, "ctx is NULL"); return LBM_EINVAL; }
   if (packed) {
     if (c->p.q_f != 27 || c->p.q_g != 19 || c->p.storage != LBM_FP32 || c->p.compute != LBM_COMPUTE_FP32 ||
-        c->p.n % 64 != 0) {
-      set_err(c->err, "the learned step needs D3Q27 x D3Q19, FP32 storage and arithmetic, n %% 64 == 0");
+        c->p.n % 64 != 0 || !learned_forcing(c)) {
+      set_err(c->err, "the learned step needs D3Q27 x D3Q19, Guo or velocity-shift forcing, FP32 storage "
+                      "and arithmetic, n %% 64 == 0");
       return LBM_EINVAL;
     }
     if ((uintptr_t)packed % 16) { set_err(c->err, "packed network must be 16-byte aligned"); return LBM_EINVAL; }

@@ -129,6 +129,7 @@ __device__ __forceinline__ C moment(int k, const C* a) {
 template <int FORCE, typename C, typename Out>
 __device__ __forceinline__ void node_features(const C* d, const C* h, const NodeMacro<C>& m, C tau_f,
                                               Out emit) {
+  static_assert(FORCE == FORCE_GUO || FORCE == FORCE_SHIFT, "learned form: Guo or velocity shift");
   emit(0, 0.f);
   emit(1, 0.f);
   emit(2, 0.f);

@@ -16,11 +16,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("STGV_LIB") or os.path.join(_HERE, "lib", "libstgv.so")
 
 LBM_OK, LBM_EINVAL, LBM_ESIZE, LBM_EHIP, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
-LBM_FORCE_GUO, LBM_FORCE_SHIFT = 0, 1
+LBM_FORCE_GUO, LBM_FORCE_SHIFT, LBM_FORCE_EDM, LBM_FORCE_HCZ = 0, 1, 2, 3
 LBM_FP32, LBM_FP16, LBM_BF16 = 0, 1, 2
 LBM_COMPUTE_FP32, LBM_COMPUTE_FP64 = 0, 1
 LBM_LAYOUT_AA, LBM_LAYOUT_AB = 0, 1
-FORCING = {"guo": LBM_FORCE_GUO, "shift": LBM_FORCE_SHIFT}
+FORCING = {"guo": LBM_FORCE_GUO, "shift": LBM_FORCE_SHIFT, "edm": LBM_FORCE_EDM, "hcz": LBM_FORCE_HCZ}
 STORAGE = {"fp32": LBM_FP32, "fp16": LBM_FP16, "bf16": LBM_BF16}
 LAYOUT = {"aa": LBM_LAYOUT_AA, "ab": LBM_LAYOUT_AB}
 COMPUTE = {"fp32": LBM_COMPUTE_FP32, "fp64": LBM_COMPUTE_FP64}

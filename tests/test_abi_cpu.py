@@ -58,7 +58,8 @@ def test_query_sizes():
 
 
 @pytest.mark.parametrize("bad", [
-    dict(n=3), dict(n=1025), dict(q_f=27, q_g=27), dict(q_f=15, q_g=7), dict(forcing=7),
+    dict(n=3), dict(n=1025), dict(q_f=27, q_g=27), dict(q_f=15, q_g=7), dict(forcing=7), dict(forcing=4),
+    dict(forcing=-1),
     dict(storage=5), dict(layout=3), dict(diag_every=-1), dict(u0=0.0), dict(u0=0.5),
     dict(u0=float("nan")), dict(re=0.0), dict(re=-5.0), dict(sc=0.0), dict(fr=0.0),
     dict(fr=float("nan")), dict(g_over_n=0.0), dict(g_over_n=float("inf")), dict(noise_amp=-1.0),
@@ -69,6 +70,13 @@ def test_invalid_parameters_are_rejected_on_the_cpu(bad):
         stgv.lbm_query_sizes(p)
     assert ei.value.status == stgv.LBM_EINVAL
     assert str(ei.value)
+
+
+@pytest.mark.parametrize("forcing", ["guo", "shift", "edm", "hcz"])
+def test_every_forcing_scheme_is_accepted(forcing):
+    p = stgv.make_params(n=32, forcing=forcing)
+    assert stgv.lbm_query_sizes(p)[0] > 0
+    assert stgv.lbm_derived(p)["G"] > 0
 
 
 def test_unstratified_limit_has_no_gravity():

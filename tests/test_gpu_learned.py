@@ -221,3 +221,17 @@ def test_learned_step_matches_oracle():
     e = lf.e.astype(float)
     dcorr_f = got[:27] - plain[:27]
     assert abs(dcorr_f.sum()) < 1e-9 * dcorr_f.size
+
+
+@pytest.mark.parametrize("forcing", ["edm", "hcz"])
+def test_learned_form_rejects_other_forcing_schemes(forcing):
+    sim = stgv.Simulation(**_learned_kw(forcing=forcing))
+    packed = packed_net(L.init_params(0), (np.zeros(47), np.ones(47), np.ones(41)))
+    with pytest.raises(stgv.LbmError) as ei:
+        sim.set_mlp(packed)
+    assert ei.value.status == stgv.LBM_EINVAL
+    coarse = torch.empty((46, 64, 64, 64), dtype=torch.float32, device=DEV)
+    x = torch.empty((64 ** 3, 47), dtype=torch.float32, device=DEV)
+    y = torch.empty((64 ** 3, 41), dtype=torch.float32, device=DEV)
+    with pytest.raises(stgv.LbmError):
+        stgv.lbm_training_pairs(sim.ctx, coarse, coarse, coarse, x, y)

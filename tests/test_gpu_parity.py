@@ -113,7 +113,7 @@ def test_init_populations_are_the_rounded_oracle_state(q_f, q_g):
 # the 32^3 Taylor-Green parity case, both forcing schemes
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("compute", ["fp32", "fp64"])
-@pytest.mark.parametrize("forcing", ["guo", "shift"])
+@pytest.mark.parametrize("forcing", ["guo", "shift", "edm", "hcz"])
 def test_tgv_parity_32(forcing, compute):
     """The 32^3 case after 100 and 200 steps.  With FP64 arithmetic every field is within
     the stated 1e-5 relative L-infinity of the FP64 oracle after 100 steps."""
@@ -134,7 +134,8 @@ def test_tgv_parity_32(forcing, compute):
             assert e100[k] <= 1e-5, (k, e100[k])
 
 
-@pytest.mark.parametrize("q_f,q_g,forcing", [(27, 7, "guo"), (19, 7, "shift"), (27, 7, "shift")])
+@pytest.mark.parametrize("q_f,q_g,forcing", [(27, 7, "guo"), (19, 7, "shift"), (27, 7, "shift"),
+                                             (27, 7, "edm"), (19, 7, "hcz")])
 @pytest.mark.parametrize("compute", ["fp32", "fp64"])
 def test_other_stencil_pairs_parity(q_f, q_g, forcing, compute):
     kw = c1_kw(q_f=q_f, q_g=q_g, forcing=forcing)
@@ -149,7 +150,7 @@ def test_other_stencil_pairs_parity(q_f, q_g, forcing, compute):
 
 
 @pytest.mark.parametrize("storage", ["fp16", "bf16"])
-@pytest.mark.parametrize("forcing", ["guo", "shift"])
+@pytest.mark.parametrize("forcing", ["guo", "shift", "edm", "hcz"])
 def test_reduced_precision_storage_parity(storage, forcing):
     """FP16 / BF16 deviation storage with FP32 arithmetic: the error is the storage's own."""
     kw = c1_kw(forcing=forcing)
@@ -167,7 +168,7 @@ def test_reduced_precision_storage_parity(storage, forcing):
 # one and two steps from a random state: population-level parity (both AA parities)
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("n", [4, 7, 20])
-@pytest.mark.parametrize("forcing", ["guo", "shift"])
+@pytest.mark.parametrize("forcing", ["guo", "shift", "edm", "hcz"])
 @pytest.mark.parametrize("q_f,q_g", [(27, 19), (19, 7)])
 def test_random_state_steps_population_parity(n, forcing, q_f, q_g):
     _random_state_parity(n, forcing, q_f, q_g)
