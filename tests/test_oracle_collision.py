@@ -13,7 +13,8 @@ import pytest
 
 from oracle import lattice as lat, micro, model
 
-PAIRS = [(27, 19), (27, 7), (19, 7)]
+# the pairs of the paper's stencil comparisons (Section 4) and of the benchmark sweep
+PAIRS = [(27, 19), (27, 7), (19, 7), (27, 27), (19, 19), (19, 15), (15, 7), (7, 27)]
 
 
 def _rand_state(rng, shape, lf, lg, amp=0.05):
@@ -54,6 +55,9 @@ FORCINGS = ["guo", "shift", "edm", "hcz"]
 @pytest.mark.parametrize("forcing", FORCINGS)
 def test_collision_mass_momentum_budget(q_f, q_g, forcing):
     """A forced BGK collision keeps mass and adds exactly F of momentum per node."""
+    if forcing == "hcz" and q_f == 7:
+        pytest.skip("the HCZ term's first moment is (1 - 1/2tau) F only on lattices with fourth-order "
+                    "isotropy; D3Q7 has none (its error is O(u^2 F))")
     lf, lg = lat.BY_Q[q_f], lat.BY_Q[q_g]
     rng = np.random.default_rng(3)
     f, g = _rand_state(rng, (64,), lf, lg)
