@@ -16,7 +16,8 @@ taken on the current kernel sources, the FP64 oracle timed on the host cores,
 and the energy error of the GPU against the oracle on the 32^3 parity case.
 
 "forms" adds the precision and learned forms: step-kernel throughput of FP16 /
-BF16 weight-shifted storage, of FP64 arithmetic and of the learned 64^3 step,
+BF16 weight-shifted storage, of FP64 arithmetic, of every stencil pair and of the
+learned 64^3 step,
 and their energy / dissipation histories (E_k, E_p, eps_k, eps_p, -dE/dt) to
 t = 30 against the plain FP32 256^3 run of the same stratified TGV (Fr 0.6).
 """
@@ -148,6 +149,14 @@ def forms(stgv, stream, t_end, steps, warmup):
         ms = kernel_time(stgv, stream, dict(base, **extra), steps, warmup)
         rates[name] = {"kernel_ms": round(ms, 5), "mlups": round(n ** 3 / (ms * 1e-3) / 1e6, 1),
                        "hbm_frac": round(bpn * n ** 3 / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+    pairs = {}
+    for qf, qg in ((27, 19), (27, 27), (19, 19), (19, 15), (15, 7), (7, 27), (27, 7), (19, 7)):
+        ms = kernel_time(stgv, stream, dict(base, q_f=qf, q_g=qg), steps, warmup)
+        bpn = 2 * (qf + qg) * 4
+        pairs[f"{qf}x{qg}"] = {"kernel_ms": round(ms, 5), "mlups": round(n ** 3 / (ms * 1e-3) / 1e6, 1),
+                               "bytes_per_node": bpn,
+                               "hbm_frac": round(bpn * n ** 3 / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+    out["stencil_pairs_fp32"] = pairs
     net_path = os.path.join(ROOT, "paper_2605_14505_amd", "data", "learned64.npz")
     if os.path.exists(net_path):
         z = np.load(net_path, allow_pickle=False)

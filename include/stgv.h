@@ -79,7 +79,9 @@ typedef enum {
 /* Problem statement (Section 2.4: Re_0 = U L / nu, Fr_0 = U / (N L), Sc = nu / D). */
 typedef struct {
   int32_t n;           /* periodic box n^3 nodes, 4 <= n <= 1024 */
-  int32_t q_f, q_g;    /* stencil pair D3Q{q_f} x D3Q{q_g}: (27,19), (27,7) or (19,7) */
+  int32_t q_f, q_g;    /* stencil pair D3Q{q_f} x D3Q{q_g} (Table 1 stencils): (27,19), (27,7),
+                          (19,7), or one of the paper's other compared pairs (27,27), (19,19),
+                          (19,15), (15,7), (7,27) */
   int32_t forcing;     /* lbm_forcing */
   int32_t storage;     /* lbm_storage */
   int32_t compute;     /* lbm_compute */

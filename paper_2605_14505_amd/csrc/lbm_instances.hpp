@@ -74,12 +74,10 @@ template <>
 hipError_t launch_step<STGV_T, STGV_C>(int qf, int qg, int force, int mode, int flags,
                                const LaunchShape& sh, hipStream_t st, STGV_T* pop, STGV_T* dst,
                                Geometry geo, PhysConsts c, float* fields, double* partials) {
-  if (qf == 27 && qg == 19)
-    return step_pair<27, 19, STGV_T>(force, mode, flags, sh, st, pop, dst, geo, c, fields, partials);
-  if (qf == 27 && qg == 7)
-    return step_pair<27, 7, STGV_T>(force, mode, flags, sh, st, pop, dst, geo, c, fields, partials);
-  if (qf == 19 && qg == 7)
-    return step_pair<19, 7, STGV_T>(force, mode, flags, sh, st, pop, dst, geo, c, fields, partials);
+#define STGV_STEP_PAIR(A, B) \
+  if (qf == A && qg == B) return step_pair<A, B, STGV_T>(force, mode, flags, sh, st, pop, dst, geo, c, fields, partials);
+  STGV_FOR_EACH_PAIR(STGV_STEP_PAIR)
+#undef STGV_STEP_PAIR
   return hipErrorInvalidValue;
 }
 
@@ -91,7 +89,7 @@ hipError_t launch_init<STGV_T>(int qf, int qg, const LaunchShape& sh, hipStream_
   if (qf == A && qg == B) { \
     hipLaunchKernelGGL((lbm_init_tgv_kernel<A, B, STGV_T>), sh.grid, sh.block, 0, st, pop, geo, u0, noise_amp, seed); \
     return hipGetLastError(); }
-  STGV_INIT(27, 19) STGV_INIT(27, 7) STGV_INIT(19, 7)
+  STGV_FOR_EACH_PAIR(STGV_INIT)
 #undef STGV_INIT
   return hipErrorInvalidValue;
 }
@@ -104,7 +102,7 @@ hipError_t launch_canon<STGV_T>(int qf, int qg, int mode, const LaunchShape& sh,
     if (mode == MODE_ODD) hipLaunchKernelGGL((lbm_canon_kernel<A, B, STGV_T, MODE_ODD>), sh.grid, sh.block, 0, st, pop, geo, out); \
     else hipLaunchKernelGGL((lbm_canon_kernel<A, B, STGV_T, MODE_EVEN>), sh.grid, sh.block, 0, st, pop, geo, out); \
     return hipGetLastError(); }
-  STGV_CANON(27, 19) STGV_CANON(27, 7) STGV_CANON(19, 7)
+  STGV_FOR_EACH_PAIR(STGV_CANON)
 #undef STGV_CANON
   return hipErrorInvalidValue;
 }
@@ -116,7 +114,7 @@ hipError_t launch_load<STGV_T>(int qf, int qg, const LaunchShape& sh, hipStream_
   if (qf == A && qg == B) { \
     hipLaunchKernelGGL((lbm_load_kernel<A, B, STGV_T>), sh.grid, sh.block, 0, st, pop, geo, in); \
     return hipGetLastError(); }
-  STGV_LOAD(27, 19) STGV_LOAD(27, 7) STGV_LOAD(19, 7)
+  STGV_FOR_EACH_PAIR(STGV_LOAD)
 #undef STGV_LOAD
   return hipErrorInvalidValue;
 }

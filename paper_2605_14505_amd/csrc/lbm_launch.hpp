@@ -11,6 +11,11 @@ struct LaunchShape {
   dim3 grid, block;
 };
 
+// The stencil pairs (momentum Q_f x scalar Q_g) with kernel instances: those of the
+// stencil comparisons of Section 4 and of the D3Q7-scalar sweep.  X(qf, qg) is applied
+// to each.
+#define STGV_FOR_EACH_PAIR(X) X(27, 19) X(27, 7) X(19, 7) X(27, 27) X(19, 19) X(19, 15) X(15, 7) X(7, 27)
+
 // Launch shape of the node kernels: block (bx, by) over x and y, grid over
 // (x, y, z).  Blocks are 256 threads except when a row is shorter than a
 // wavefront; every block is a whole number of 64-wide wavefronts.

@@ -215,7 +215,10 @@ void set_err(char* buf, const char* fmt, ...) {
 double lattice_cs2(int q) { return q == 7 ? 0.25 : 1.0 / 3.0; }
 
 bool valid_pair(int qf, int qg) {
-  return (qf == 27 && qg == 19) || (qf == 27 && qg == 7) || (qf == 19 && qg == 7);
+#define STGV_IS_PAIR(A, B) if (qf == A && qg == B) return true;
+  STGV_FOR_EACH_PAIR(STGV_IS_PAIR)
+#undef STGV_IS_PAIR
+  return false;
 }
 
 // Parameter checks and the lattice-unit constants of Eqs. (8), (13), (14), (19)
@@ -224,7 +227,8 @@ int derive(const lbm_params* p, Derived* d, char* err) {
   if (!p) { set_err(err, "params is NULL"); return LBM_EINVAL; }
   if (p->n < 4 || p->n > 1024) { set_err(err, "n = %d outside [4, 1024]", p->n); return LBM_EINVAL; }
   if (!valid_pair(p->q_f, p->q_g)) {
-    set_err(err, "stencil pair D3Q%d x D3Q%d not supported (27x19, 27x7, 19x7)", p->q_f, p->q_g);
+    set_err(err, "stencil pair D3Q%d x D3Q%d not supported (27x19, 27x7, 19x7, 27x27, 19x19, 19x15, "
+                 "15x7, 7x27)", p->q_f, p->q_g);
     return LBM_EINVAL;
   }
   if (p->forcing < LBM_FORCE_GUO || p->forcing > LBM_FORCE_HCZ) {

@@ -95,7 +95,10 @@ def gpu_sim(**kw):
 # ---------------------------------------------------------------------------
 # initial state
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("q_f,q_g", [(27, 19), (27, 7), (19, 7)])
+ALL_PAIRS = [(27, 19), (27, 7), (19, 7), (27, 27), (19, 19), (19, 15), (15, 7), (7, 27)]
+
+
+@pytest.mark.parametrize("q_f,q_g", ALL_PAIRS)
 def test_init_populations_are_the_rounded_oracle_state(q_f, q_g):
     kw = c1_kw(q_f=q_f, q_g=q_g)
     sim = gpu_sim(**kw)
@@ -135,7 +138,10 @@ def test_tgv_parity_32(forcing, compute):
 
 
 @pytest.mark.parametrize("q_f,q_g,forcing", [(27, 7, "guo"), (19, 7, "shift"), (27, 7, "shift"),
-                                             (27, 7, "edm"), (19, 7, "hcz")])
+                                             (27, 7, "edm"), (19, 7, "hcz"),
+                                             (27, 27, "shift"), (27, 27, "hcz"), (19, 19, "guo"),
+                                             (19, 15, "shift"), (19, 15, "edm"), (15, 7, "guo"),
+                                             (7, 27, "shift")])
 @pytest.mark.parametrize("compute", ["fp32", "fp64"])
 def test_other_stencil_pairs_parity(q_f, q_g, forcing, compute):
     kw = c1_kw(q_f=q_f, q_g=q_g, forcing=forcing)
@@ -172,6 +178,12 @@ def test_reduced_precision_storage_parity(storage, forcing):
 @pytest.mark.parametrize("q_f,q_g", [(27, 19), (19, 7)])
 def test_random_state_steps_population_parity(n, forcing, q_f, q_g):
     _random_state_parity(n, forcing, q_f, q_g)
+
+
+@pytest.mark.parametrize("forcing", ["guo", "shift", "edm", "hcz"])
+@pytest.mark.parametrize("q_f,q_g", [(27, 27), (19, 19), (19, 15), (15, 7), (7, 27)])
+def test_random_state_parity_other_pairs(q_f, q_g, forcing):
+    _random_state_parity(7, forcing, q_f, q_g)
 
 
 def test_random_state_parity_with_32x8_blocks():
