@@ -114,23 +114,36 @@ def kernel_time(stgv, stream, kw, steps, warmup, packed=None):
     return ev0.elapsed_time(ev1) / steps
 
 
-def history(stgv, kw, t_end, diag_every, packed=None):
-    """Diagnostic records of one run to t_end (convective times L/U)."""
+def history(stgv, kw, t_end, diag_every, packed=None, spectrum_at=None):
+    """Diagnostic records of one run to t_end (convective times L/U); with spectrum_at,
+    also the kinetic-energy spectrum at that time and the time its call took (ms)."""
     import torch
     from paper_2605_14505_amd import learned
-    steps = int(round(t_end * learned.steps_per_unit_time(kw["n"], kw["u0"])))
+    per = learned.steps_per_unit_time(kw["n"], kw["u0"])
+    steps = int(round(t_end * per))
+    stop = int(round(spectrum_at * per)) if spectrum_at is not None else None
     sim = stgv.Simulation(diag_every=diag_every, **kw)
     if packed is not None:
         sim.set_mlp(packed)
+    spec = None
     done = 0
     while done < steps:
-        k = min(2048, steps - done)
+        k = min(2048, steps - done, (stop - done) if stop is not None and stop > done else steps)
         sim.step(k)
         done += k
+        if stop is not None and done == stop:
+            sim.spectrum()                                   # plan and work buffer
+            stream = torch.cuda.current_stream()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            e = sim.spectrum()
+            ev1.record(stream)
+            ev1.synchronize()
+            spec = (e.cpu().numpy(), ev0.elapsed_time(ev1))
     torch.cuda.synchronize()
     recs = sim.diagnostics(raise_unstable=False)
     sim.close()
-    return recs
+    return (recs, spec) if spectrum_at is not None else recs
 
 
 def forms(stgv, stream, t_end, steps, warmup):
@@ -170,7 +183,17 @@ def forms(stgv, stream, t_end, steps, warmup):
         rates[name] = {"kernel_ms": round(ms, 5), "mlups": round(nc ** 3 / (ms * 1e-3) / 1e6, 1)}
     out["throughput"] = rates
     de_c = max(1, int(round(t_end * learned.steps_per_unit_time(nc) / 100)))
-    ref = history(stgv, base, t_end, 4 * de_c)
+    ref, (spec, spec_ms) = history(stgv, base, t_end, 4 * de_c, spectrum_at=min(15.0, t_end))
+    _, _, post = stgv.lbm_postprocess(ref, 1600.0, 0.6, 30.0)
+    k = np.arange(1, spec.size)
+    sel = (k >= 4) & (k <= 24)
+    slope = float(np.polyfit(np.log(k[sel]), np.log(spec[1:][sel]), 1)[0])
+    out["postprocess_fp32_256"] = {
+        "gamma_b": round(post["gamma_b"], 5), "fr_t": round(post["fr_t"], 5),
+        "r_max": round(post["r_max"], 4), "t_r_max": round(post["t_r_max"], 3),
+        "spectrum_t": min(15.0, t_end), "spectrum_ms": round(spec_ms, 3),
+        "spectrum_slope_k4_24": round(slope, 3),
+        "spectrum_head": [float(f"{v:.4e}") for v in spec[:12]]}
     errs = {}
     for name, extra in (("fp16", {"storage": "fp16"}), ("bf16", {"storage": "bf16"})):
         errs[name] = learned.series_errors(history(stgv, dict(base, **extra), t_end, 4 * de_c), ref)

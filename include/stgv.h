@@ -239,6 +239,45 @@ int lbm_training_pairs(lbm_ctx* coarse, const float* a_dev, const float* b_dev, 
  * the fused learned step.  packed_dev must stay valid while attached. */
 int lbm_set_mlp(lbm_ctx* ctx, const void* packed_dev);
 
+/* ------------------------------------------------------------------------
+ * Post-processing (Section 4): the quantities derived from the diagnostic
+ * histories and the kinetic-energy spectrum.  Physical units (U = L = 1 on the
+ * 2 pi box): nu = 1/Re, N = 1/Fr.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  double gamma_b;      /* bulk flux coefficient int eps_p dt / int eps_k dt over [0, t_end] */
+  double fr_t;         /* turbulent Froude number int eps_k dt / (N int E_k dt) over [0, t_end] */
+  double r_max;        /* largest buoyancy Reynolds number eps_k / (nu N^2) among the records */
+  double t_r_max;      /* its time */
+  int32_t used;        /* records with t <= t_end entering the integrals */
+  int32_t reserved;
+} lbm_post;
+
+/* From `count` >= 2 records with increasing t: per-record buoyancy Reynolds
+ * number R = eps_k / (nu N^2) into r_out and flux coefficient Gamma = eps_p /
+ * eps_k into gamma_out (either may be NULL), and the bulk quantities into *out;
+ * integrals are trapezoid sums over the records with t <= t_end.  fr may be
+ * +inf (N = 0: R and Fr_t are +inf).  Host memory only, CPU only.  LBM_EINVAL
+ * for a bad argument or non-increasing times. */
+int lbm_postprocess(const lbm_diag* recs, int32_t count, double re, double fr, double t_end,
+                    double* r_out, double* gamma_out, lbm_post* out);
+
+/* Number of spectral shells for an n^3 box: k = 0 .. round(sqrt(3) n / 2), or -1
+ * for n outside [4, 1024]. */
+int32_t lbm_spectrum_shells(int32_t n);
+
+/* Device work bytes of lbm_ke_spectrum for an n^3 box (velocity fields, the FFT's
+ * complex output and work space, per-block partial sums).  Creates and caches the
+ * rocFFT plan for n, so it needs the GPU; LBM_EHIP if rocFFT fails. */
+int lbm_spectrum_work_bytes(int32_t n, size_t* bytes);
+
+/* Kinetic-energy spectrum of the current state, E(k) = sum over wavevectors with
+ * round(|k|) = k of |u_hat|^2 / 2, u_hat = FFT(u / U) / n^3 (u of Eq. (7)), so that
+ * sum_k E(k) = E_k.  shells_dev: lbm_spectrum_shells(n) FP64 values (device); work:
+ * lbm_spectrum_work_bytes bytes (device, 256-byte aligned), both caller-owned.
+ * Queued on the context's stream (the result is valid after it synchronises). */
+int lbm_ke_spectrum(lbm_ctx* ctx, void* work_dev, size_t work_bytes, double* shells_dev);
+
 int64_t lbm_get_step(const lbm_ctx* ctx);
 const char* lbm_last_error(const lbm_ctx* ctx);
 const char* lbm_status_string(int status);

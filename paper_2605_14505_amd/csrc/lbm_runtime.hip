@@ -11,6 +11,7 @@
 
 #include "../../include/stgv.h"
 #include "learned.hpp"
+#include "postproc.hpp"
 #include "lbm_device.hpp"
 #include "lbm_launch.hpp"
 #include "mlp_device.hpp"
@@ -787,6 +788,73 @@ int lbm_set_mlp(lbm_ctx* c, const void* packed) {
     if ((uintptr_t)packed % 16) { set_err(c->err, "packed network must be 16-byte aligned"); return LBM_EINVAL; }
   }
   c->mlp = packed;
+  return LBM_OK;
+}
+
+int lbm_postprocess(const lbm_diag* recs, int32_t count, double re, double fr, double t_end, double* r_out,
+                    double* gamma_out, lbm_post* out) {
+  if (!recs || !out || count < 2 || !(re > 0.0) || !(fr > 0.0) || std::isnan(t_end)) {
+    set_err(g_err, "invalid argument"); return LBM_EINVAL;
+  }
+  for (int32_t i = 1; i < count; ++i)
+    if (!(recs[i].t > recs[i - 1].t)) { set_err(g_err, "record times must increase (record %d)", i); return LBM_EINVAL; }
+  const double nu = 1.0 / re, nb = 1.0 / fr;          // fr = +inf gives N = 0
+  lbm_post post{};
+  post.r_max = -1.0;
+  for (int32_t i = 0; i < count; ++i) {
+    const double r = recs[i].eps_k / (nu * nb * nb);
+    if (r_out) r_out[i] = r;
+    if (gamma_out) gamma_out[i] = recs[i].eps_p / recs[i].eps_k;
+    if (r > post.r_max) { post.r_max = r; post.t_r_max = recs[i].t; }
+  }
+  double ip = 0.0, ik = 0.0, ie = 0.0;
+  int32_t used = 1;
+  for (int32_t i = 1; i < count && recs[i].t <= t_end; ++i, ++used) {
+    const double h = 0.5 * (recs[i].t - recs[i - 1].t);
+    ip += h * (recs[i].eps_p + recs[i - 1].eps_p);
+    ik += h * (recs[i].eps_k + recs[i - 1].eps_k);
+    ie += h * (recs[i].ek + recs[i - 1].ek);
+  }
+  post.gamma_b = ip / ik;
+  post.fr_t = ik / (nb * ie);
+  post.used = used;
+  *out = post;
+  return LBM_OK;
+}
+
+int32_t lbm_spectrum_shells(int32_t n) { return (n < 4 || n > 1024) ? -1 : spectrum_shells(n); }
+
+static size_t spectrum_fields_bytes(int n) { return align_up((size_t)5 * n * n * n * sizeof(float), kAlign); }
+
+int lbm_spectrum_work_bytes(int32_t n, size_t* bytes) {
+  if (!bytes || n < 4 || n > 1024) { set_err(g_err, "invalid argument"); return LBM_EINVAL; }
+  char err[512] = {0};
+  const size_t extra = spectrum_extra_bytes(n, err);
+  if (!extra) { set_err(g_err, "%s", err); return LBM_EHIP; }
+  *bytes = spectrum_fields_bytes(n) + extra;
+  return LBM_OK;
+}
+
+int lbm_ke_spectrum(lbm_ctx* c, void* work, size_t work_bytes, double* shells) {
+  if (!c) { set_err(g_err, "ctx is NULL"); return LBM_EINVAL; }
+  if (!work || !shells || (uintptr_t)work % kAlign) {
+    set_err(c->err, "work (256-byte aligned) and shells must be device buffers"); return LBM_EINVAL;
+  }
+  const int n = c->p.n;
+  const size_t fb = spectrum_fields_bytes(n);
+  if (work_bytes < fb) { set_err(c->err, "spectrum work buffer too small"); return LBM_ESIZE; }
+  float* fields = static_cast<float*>(work);
+  const int mode = current_mode(c);
+  char* src = current_array(c);
+  hipError_t e = launch_node(c, mode, K_FIELDS, src, src, fields, nullptr);
+  if (e != hipSuccess) return hip_fail(c, e, "fields kernel");
+  const size_t n3 = (size_t)n * n * n;
+  char err[512] = {0};
+  e = spectrum_launch(fields + n3, fields + 2 * n3, fields + 3 * n3, n, c->p.u0, static_cast<char*>(work) + fb,
+                      work_bytes - fb, shells, c->stream, err);
+  if (e == hipErrorInvalidValue && err[0]) { set_err(c->err, "%s", err); return LBM_ESIZE; }
+  if (e == hipErrorUnknown && err[0]) { set_err(c->err, "%s", err); return LBM_EHIP; }
+  if (e != hipSuccess) return hip_fail(c, e, "spectrum kernels");
   return LBM_OK;
 }
 

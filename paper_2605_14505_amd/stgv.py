@@ -49,6 +49,14 @@ class lbm_diag(ctypes.Structure):
         return d
 
 
+class lbm_post(ctypes.Structure):
+    _fields_ = [("gamma_b", ctypes.c_double), ("fr_t", ctypes.c_double), ("r_max", ctypes.c_double),
+                ("t_r_max", ctypes.c_double), ("used", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 class LbmError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"{_status_name(status)}: {message}")
@@ -84,6 +92,10 @@ def _load():
         "lbm_restrict": (ctypes.c_int, [vp, vp, vp]),
         "lbm_training_pairs": (ctypes.c_int, [vp, vp, vp, vp, vp, vp]),
         "lbm_set_mlp": (ctypes.c_int, [vp, vp]),
+        "lbm_postprocess": (ctypes.c_int, [P(lbm_diag), i32, dbl, dbl, dbl, P(dbl), P(dbl), P(lbm_post)]),
+        "lbm_spectrum_shells": (i32, [i32]),
+        "lbm_spectrum_work_bytes": (ctypes.c_int, [i32, P(sz)]),
+        "lbm_ke_spectrum": (ctypes.c_int, [vp, vp, sz, vp]),
         "lbm_get_step": (i64, [vp]),
         "lbm_last_error": (ctypes.c_char_p, [vp]),
         "lbm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -102,7 +114,8 @@ EXPORTED = ("lbm_query_sizes", "lbm_derived", "lbm_init_tgv", "lbm_step", "lbm_s
             "lbm_status_string", "lbm_destroy", "lbm_mlp_packed_bytes", "lbm_mlp_pack",
             "lbm_mlp_forward", "lbm_mlp_grad_work_bytes", "lbm_mlp_grad", "lbm_mlp_adam",
             "lbm_mlp_norm_work_bytes", "lbm_mlp_norm", "lbm_restrict", "lbm_training_pairs",
-            "lbm_set_mlp")
+            "lbm_set_mlp", "lbm_postprocess", "lbm_spectrum_shells", "lbm_spectrum_work_bytes",
+            "lbm_ke_spectrum")
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS, MLP_NORM = 47, 64, 41, 9897, 135
 
 
@@ -242,6 +255,42 @@ def lbm_set_mlp(ctx, packed):
     _check(LIB.lbm_set_mlp(ctx, _ptr(packed)), ctx)
 
 
+def _diag_array(recs):
+    arr = (lbm_diag * len(recs))()
+    for i, r in enumerate(recs):
+        for k, _ in lbm_diag._fields_:
+            if k == "mom":
+                arr[i].mom[:] = list(r.get("mom", (0.0, 0.0, 0.0)))
+            else:
+                setattr(arr[i], k, r.get(k, 0))
+    return arr
+
+
+def lbm_postprocess(recs, re, fr, t_end=30.0):
+    """recs: diagnostic records (dicts as returned by lbm_diagnostics).  Returns
+    (R per record, Gamma per record, bulk summary dict)."""
+    n = len(recs)
+    arr = _diag_array(recs)
+    r_out, g_out, post = (ctypes.c_double * n)(), (ctypes.c_double * n)(), lbm_post()
+    _check(LIB.lbm_postprocess(arr, n, re, math.inf if fr is None else fr, t_end, r_out, g_out,
+                               ctypes.byref(post)))
+    return list(r_out), list(g_out), post.as_dict()
+
+
+def lbm_spectrum_shells(n):
+    return LIB.lbm_spectrum_shells(n)
+
+
+def lbm_spectrum_work_bytes(n):
+    b = ctypes.c_size_t()
+    _check(LIB.lbm_spectrum_work_bytes(n, ctypes.byref(b)))
+    return b.value
+
+
+def lbm_ke_spectrum(ctx, work, shells):
+    _check(LIB.lbm_ke_spectrum(ctx, _ptr(work), work.numel() * work.element_size(), _ptr(shells)), ctx)
+
+
 def lbm_get_step(ctx):
     return LIB.lbm_get_step(ctx)
 
@@ -294,6 +343,14 @@ class Simulation:
         """Attach a packed network (a uint8 device tensor kept alive by the caller), or None."""
         self._mlp = packed
         lbm_set_mlp(self.ctx, packed)
+
+    def spectrum(self):
+        """Kinetic-energy spectrum E(k), k = 0 .. round(sqrt(3) n / 2), FP64 on the device."""
+        if getattr(self, "_spec_work", None) is None:
+            self._spec_work = torch.empty(lbm_spectrum_work_bytes(self.n), dtype=torch.uint8, device=self.device)
+        out = torch.empty(lbm_spectrum_shells(self.n), dtype=torch.float64, device=self.device)
+        lbm_ke_spectrum(self.ctx, self._spec_work, out)
+        return out
 
     def restrict_to(self, coarse):
         """This (fine) state restricted to the grid of `coarse` (a Simulation), FP32 deviations."""

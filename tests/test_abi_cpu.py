@@ -17,7 +17,7 @@ HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))
 
 def test_library_exports_every_declared_entry_point():
     text = open(HEADER).read()
-    declared = set(re.findall(r"^\s*(?:int|int64_t|size_t|void|const char\*)\s+(lbm_\w+)\s*\(", text, re.M))
+    declared = set(re.findall(r"^\s*(?:int|int32_t|int64_t|size_t|void|const char\*)\s+(lbm_\w+)\s*\(", text, re.M))
     assert declared, "no declarations parsed"
     assert declared == set(stgv.EXPORTED)
     for name in declared:
@@ -58,7 +58,8 @@ def test_query_sizes():
 
 
 @pytest.mark.parametrize("bad", [
-    dict(n=3), dict(n=1025), dict(q_f=27, q_g=27), dict(q_f=15, q_g=7), dict(forcing=7), dict(forcing=4),
+    dict(n=3), dict(n=1025), dict(q_f=27, q_g=15), dict(q_f=7, q_g=7), dict(q_f=15, q_g=19),
+    dict(q_f=9, q_g=7), dict(forcing=7), dict(forcing=4),
     dict(forcing=-1),
     dict(storage=5), dict(layout=3), dict(diag_every=-1), dict(u0=0.0), dict(u0=0.5),
     dict(u0=float("nan")), dict(re=0.0), dict(re=-5.0), dict(sc=0.0), dict(fr=0.0),
