@@ -31,7 +31,6 @@ enum KernelFlags : int {
   K_COLLIDE = 1,    // collide and stream (the time step)
   K_FIELDS = 2,     // write rho - 1, u_x, u_y, u_z, rho' per node
   K_PARTIALS = 4,   // write per-block diagnostic partials
-  K_LEARNED = 8,    // add the learned moment correction (D3Q27 x D3Q19, one wavefront per block)
 };
 
 // Per-block diagnostic partials written by the diagnostic step / moments kernels.
@@ -253,12 +252,11 @@ struct NodeMacro {
   C vx, vy, vz; // velocity of the momentum equilibrium the collision relaxes to
 };
 
-template <int QF, int QG, int FORCE, typename C>
-__device__ __forceinline__ void node_macro(const C* f, const C* g, const PhysConsts& c,
-                                           NodeMacro<C>& m) {
-  C drho, jx, jy, jz;
-  pair_moments<QF>(f, drho, jx, jy, jz);
-  const C dsig = pair_sum<QG>(g);
+// The node's moments from its population sums: drho = sum f - 1 (deviations),
+// j = sum e f, dsig = sum g - 1.
+template <int FORCE, typename C>
+__device__ __forceinline__ void macro_from_sums(C drho, C jx, C jy, C jz, C dsig, const PhysConsts& c,
+                                                NodeMacro<C>& m) {
   const C rho = C(1) + drho;                  // Eq. (6), rho_0 = 1 plus deviation
   const C inv_rho = C(1) / rho;
   const C upz = jz * inv_rho;
@@ -275,6 +273,15 @@ __device__ __forceinline__ void node_macro(const C* f, const C* g, const PhysCon
   if (FORCE == FORCE_SHIFT) m.vz = upz + (C)c.tau_f * Fz * inv_rho;  // Shan-Chen shift, Eq. (10) (tau F / rho)
   else if (FORCE == FORCE_EDM) m.vz = upz;                            // EDM relaxes to f^eq(u')
   else m.vz = m.uz;                                                   // Guo, HCZ: u of Eq. (7)
+}
+
+template <int QF, int QG, int FORCE, typename C>
+__device__ __forceinline__ void node_macro(const C* f, const C* g, const PhysConsts& c,
+                                           NodeMacro<C>& m) {
+  C drho, jx, jy, jz;
+  pair_moments<QF>(f, drho, jx, jy, jz);
+  const C dsig = pair_sum<QG>(g);
+  macro_from_sums<FORCE>(drho, jx, jy, jz, dsig, c, m);
 }
 
 template <int QF, int QG, int FORCE, typename C>
@@ -312,6 +319,15 @@ struct Collision {
   __device__ __forceinline__ C geq(int j) const {
     const C xi = icg * dot_e(SG::ex[j], SG::ey[j], SG::ez[j], tx, ty, tz);
     return C(SG::w[j]) * (m.rho_p + conc * (base_g + xi * (C(1) + C(0.5) * xi)));
+  }
+  // the same equilibria from e.v_eq (f) or e.v_theta (g) and the weight w
+  __device__ __forceinline__ C feq_of(C eu, C w) const {
+    const C xi = icf * eu;
+    return w * (base_f + m.rho * xi * (C(1) + C(0.5) * xi));
+  }
+  __device__ __forceinline__ C geq_of(C eu, C w) const {
+    const C xi = icg * eu;
+    return w * (m.rho_p + conc * (base_g + xi * (C(1) + C(0.5) * xi)));
   }
   // f[i] <- d_i = f_i^eq - f_i and g[j] <- h_j = g_j^eq - g_j
   __device__ __forceinline__ void relaxation_increments(C* f, C* g) const {
@@ -380,6 +396,33 @@ __device__ __forceinline__ void node_collide(C* f, C* g, const PhysConsts& c,
   const Collision<QF, QG, FORCE, C> col(c, m);
   col.relaxation_increments(f, g);
   col.finish(f, g);
+}
+
+// Diagnostic outputs of one node: the five fields (rho - 1, u, rho') and its
+// contributions to the block partials.
+template <typename C>
+__device__ __forceinline__ void write_fields(const NodeMacro<C>& m, float* __restrict__ fields, uint32_t node,
+                                             int64_t n3) {
+  fields[node] = (float)m.drho;
+  fields[n3 + node] = (float)m.ux;
+  fields[2 * n3 + node] = (float)m.uy;
+  fields[3 * n3 + node] = (float)m.uz;
+  fields[4 * n3 + node] = (float)m.rho_p;
+}
+
+template <typename C>
+__device__ __forceinline__ void node_partials(const NodeMacro<C>& m, const PhysConsts& c, double* acc) {
+  const C u2 = m.ux * m.ux + m.uy * m.uy + m.uz * m.uz;
+  const C ep = (C)c.g_over_n * m.rho_p;
+  acc[P_EK] = 0.5 * (double)u2;
+  acc[P_EP] = 0.5 * (double)(ep * ep);
+  acc[P_DRHO] = (double)m.drho;
+  acc[P_DSIG] = (double)m.dsig;
+  acc[P_MX] = (double)m.jx;
+  acc[P_MY] = (double)m.jy;
+  acc[P_MZ] = (double)(m.jz + C(0.5) * m.Fz);
+  acc[P_UMAX2] = (double)u2;
+  acc[P_NONFINITE] = (isfinite(m.rho) && isfinite(u2) && isfinite(m.rho_p)) ? 0.0 : 1.0;
 }
 
 // ---------------------------------------------------------------------------

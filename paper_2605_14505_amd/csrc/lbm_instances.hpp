@@ -16,7 +16,7 @@ template <int QF, int QG, int FORCE, typename T, int MODE, int FLAGS>
 hipError_t go_step(const LaunchShape& sh, hipStream_t st, T* pop, T* dst, Geometry geo,
                    PhysConsts c, float* fields, double* partials) {
   hipLaunchKernelGGL((lbm_step_kernel<QF, QG, FORCE, T, STGV_C, MODE, FLAGS>), sh.grid, sh.block,
-                     0, st, pop, dst, geo, c, fields, partials, nullptr);
+                     0, st, pop, dst, geo, c, fields, partials);
   return hipGetLastError();
 }
 

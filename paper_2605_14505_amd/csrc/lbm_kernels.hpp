@@ -1,7 +1,6 @@
 // Kernels of the DDF lattice Boltzmann step and its diagnostics (gfx950).
 #pragma once
 #include "lbm_device.hpp"
-#include "mlp_device.hpp"
 
 namespace stgv {
 
@@ -26,8 +25,7 @@ namespace stgv {
 template <int QF, int QG, int FORCE, typename T, typename C, int MODE, int FLAGS>
 __global__ STGV_STEP_BOUNDS void lbm_step_kernel(T* pop, T* dst, Geometry geo,
                                                        PhysConsts c, float* __restrict__ fields,
-                                                       double* __restrict__ partials,
-                                                       const void* __restrict__ net) {
+                                                       double* __restrict__ partials) {
   const int n = geo.n;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -47,71 +45,9 @@ __global__ STGV_STEP_BOUNDS void lbm_step_kernel(T* pop, T* dst, Geometry geo,
     gather<QG, T, MODE>(g, pop, QF, ix, geo.stride);
     NodeMacro<C> m;
     node_macro<QF, QG, FORCE>(f, g, c, m);
-    if (FLAGS & K_FIELDS) {
-      const int64_t n3 = (int64_t)n * n * n;
-      fields[ix.base] = (float)m.drho;
-      fields[n3 + ix.base] = (float)m.ux;
-      fields[2 * n3 + ix.base] = (float)m.uy;
-      fields[3 * n3 + ix.base] = (float)m.uz;
-      fields[4 * n3 + ix.base] = (float)m.rho_p;
-    }
-    if (kPart) {
-      const C u2 = m.ux * m.ux + m.uy * m.uy + m.uz * m.uz;
-      const C ep = (C)c.g_over_n * m.rho_p;
-      acc[P_EK] = 0.5 * (double)u2;
-      acc[P_EP] = 0.5 * (double)(ep * ep);
-      acc[P_DRHO] = (double)m.drho;
-      acc[P_DSIG] = (double)m.dsig;
-      acc[P_MX] = (double)m.jx;
-      acc[P_MY] = (double)m.jy;
-      acc[P_MZ] = (double)(m.jz + C(0.5) * m.Fz);
-      acc[P_UMAX2] = (double)u2;
-      acc[P_NONFINITE] = (isfinite(m.rho) && isfinite(u2) && isfinite(m.rho_p)) ? 0.0 : 1.0;
-    }
-    if constexpr ((FLAGS & K_LEARNED) != 0) {
-      // Learned correction: features from the relaxation increments, the network on
-      // the block's 64 nodes (BF16 MFMA), M^-1 [0, dm] added to the post-collision
-      // populations.  Launched with 64-thread blocks on boxes with n % 64 == 0, so
-      // every thread is active and reaches the block barriers of the network.
-      static_assert(QF == 27 && QG == 19, "the learned correction is defined for D3Q27 x D3Q19");
-      using namespace mlp;
-      const Packed* P = static_cast<const Packed*>(net);
-      __shared__ __attribute__((aligned(16))) uint16_t xs[64 * LDS_PITCH];
-      __shared__ __attribute__((aligned(16))) uint16_t hs[64 * LDS_PITCH];
-      __shared__ float os[64 * N_OUT];
-      const int lane = threadIdx.x;
-      const Collision<QF, QG, FORCE, C> col(c, m);
-      col.relaxation_increments(f, g);
-      {
-        uint16_t* row = xs + lane * LDS_PITCH;
-        node_features<FORCE>(f, g, m, col.tau_f, [&](int k, float v) {
-          row[k] = bf16_bits((v - P->x_mean[k]) * P->x_iscale[k]);
-        });
-        for (int k = N_IN; k < 64; ++k) row[k] = 0;
-      }
-      col.finish(f, g);
-      __syncthreads();
-      mlp_forward_wave(P, xs, hs, os);
-      const float* dm = os + lane * N_OUT;
-#pragma unroll
-      for (int i = 0; i < 27; ++i) {
-        C a = C(0);
-#pragma unroll
-        for (int k = NCF; k < 27; ++k)
-          if (MINV_F.v[i][k] != 0.f) a += C(MINV_F.v[i][k]) * (C)dm[k - NCF];
-        f[i] += a;
-      }
-#pragma unroll
-      for (int j = 0; j < 19; ++j) {
-        C a = C(0);
-#pragma unroll
-        for (int k = NCG; k < 19; ++k)
-          if (MINV_G.v[j][k] != 0.f) a += C(MINV_G.v[j][k]) * (C)dm[27 - NCF + k - NCG];
-        g[j] += a;
-      }
-      scatter<QF, T, MODE>(f, dst, 0, ix, geo.stride);
-      scatter<QG, T, MODE>(g, dst, QF, ix, geo.stride);
-    } else if (FLAGS & K_COLLIDE) {
+    if (FLAGS & K_FIELDS) write_fields(m, fields, ix.base, (int64_t)n * n * n);
+    if (kPart) node_partials(m, c, acc);
+    if (FLAGS & K_COLLIDE) {
       node_collide<QF, QG, FORCE>(f, g, c, m);
       scatter<QF, T, MODE>(f, dst, 0, ix, geo.stride);
       scatter<QG, T, MODE>(g, dst, QF, ix, geo.stride);

@@ -303,7 +303,8 @@ Sizes sizes_of(const lbm_params* p) {
   s.pop_bytes = (size_t)(arrays * s.stride) * s.elem;
   const LaunchShape sh = node_shape(p->n);
   s.nsp = (int64_t)sh.grid.x * sh.grid.y * sh.grid.z;
-  s.nsp_learned = (p->n % 64 == 0) ? (int64_t)(p->n / 64) * p->n * p->n : 0;
+  // the learned step runs 256-thread blocks of 128 nodes
+  s.nsp_learned = (p->n % 64 == 0) ? (int64_t)p->n * p->n * p->n / 128 : 0;
   const int64_t nsp_max = s.nsp > s.nsp_learned ? s.nsp : s.nsp_learned;
   s.nfp = (int64_t)((p->n + FD_TX - 1) / FD_TX) * ((p->n + FD_TY - 1) / FD_TY) * ((p->n + FD_ZC - 1) / FD_ZC);
   size_t off = 0;

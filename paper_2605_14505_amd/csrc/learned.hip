@@ -9,6 +9,8 @@
 namespace stgv {
 namespace mlp {
 
+__constant__ StepTables kStepTables = make_step_tables();
+
 // ---------------------------------------------------------------------------
 // packing: FP32 master parameters (W1 [64][47], b1, W2 [64][64], b2, W3 [41][64],
 // b3) and the normalisation (x_mean[47], x_iscale[47], y_scale[41]) -> Packed
@@ -47,6 +49,27 @@ __global__ __launch_bounds__(256) void pack_kernel(const float* __restrict__ the
   for (int t = threadIdx.x; t < K_IN; t += blockDim.x) {
     P->x_mean[t] = t < N_IN ? norm[t] : 0.f;
     P->x_iscale[t] = t < N_IN ? norm[N_IN + t] : 0.f;
+  }
+  // the fused step's copies: logical row k at physical row perm_row(k); the output
+  // layer carries y_scale so that its result is the moment correction itself
+  for (int t = threadIdx.x; t < 64 * K_IN; t += blockDim.x) {
+    const int row = t / K_IN, c = t % K_IN, k = perm_row(row);
+    P->w1p[t] = c < N_IN ? bf16_bits(W1[k * N_IN + c]) : 0;
+    P->tab.feat[t] = kStepTables.feat[t];
+    P->tab.minv[t] = kStepTables.minv[t];
+  }
+  for (int t = threadIdx.x; t < 64 * N_HID; t += blockDim.x) {
+    const int row = t / N_HID, c = t % N_HID, k = perm_row(row);
+    P->w2p[t] = bf16_bits(W2[k * N_HID + c]);
+    P->w3p[t] = k < N_OUT ? bf16_bits(norm[2 * N_IN + k] * W3[k * N_HID + c]) : 0;
+  }
+  for (int row = threadIdx.x; row < 64; row += blockDim.x) {
+    const int k = perm_row(row);
+    P->b1p[row] = b1[k];
+    P->b2p[row] = b2[k];
+    P->b3p[row] = k < N_OUT ? norm[2 * N_IN + k] * b3[k] : 0.f;
+    P->x_mean_p[row] = k < N_IN ? norm[k] : 0.f;
+    P->x_iscale_p[row] = k < N_IN ? norm[N_IN + k] : 0.f;
   }
 }
 

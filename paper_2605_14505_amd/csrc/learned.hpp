@@ -20,7 +20,8 @@ hipError_t mlp_launch_restrict(int storage, const void* fine, int mode, Geometry
                                int nc, float sf, float sg, float* out, hipStream_t st);
 hipError_t mlp_launch_pairs(int forcing, const float* a, const float* b, const float* c, int nc,
                             PhysConsts pc, float* x, float* y, hipStream_t st);
-// The fused learned step of a D3Q27 x D3Q19 FP32 state (lbm_kernels.hpp, K_LEARNED).
+// The fused learned step of a D3Q27 x D3Q19 FP32 state, n % 64 == 0 (learned_step.hip);
+// flags & K_PARTIALS selects the diagnostic variant.
 hipError_t launch_learned_step(int forcing, int mode, int flags, int n, hipStream_t st, float* pop,
                                float* dst, Geometry geo, PhysConsts c, float* fields, double* partials,
                                const void* packed);

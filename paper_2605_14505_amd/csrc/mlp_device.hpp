@@ -81,7 +81,10 @@ template <int Q>
 struct Inverse { float v[Q][Q]; };
 
 template <int Q>
-constexpr Inverse<Q> make_inverse() {
+struct InverseFrac { Frac v[Q][Q]; };
+
+template <int Q>
+constexpr InverseFrac<Q> make_inverse_frac() {
   Frac A[Q][2 * Q] = {};
   for (int r = 0; r < Q; ++r)
     for (int c = 0; c < 2 * Q; ++c)
@@ -98,9 +101,22 @@ constexpr Inverse<Q> make_inverse() {
       for (int c = 0; c < 2 * Q; ++c) A[r][c] = fsub(A[r][c], fmul(fac, A[col][c]));
     }
   }
+  InverseFrac<Q> out{};
+  for (int r = 0; r < Q; ++r)
+    for (int c = 0; c < Q; ++c) out.v[r][c] = A[r][Q + c];
+  return out;
+}
+constexpr InverseFrac<27> MINV_F_FRAC = make_inverse_frac<27>();
+constexpr InverseFrac<19> MINV_G_FRAC = make_inverse_frac<19>();
+
+template <int Q>
+constexpr Frac inverse_entry(int r, int c) { return Q == 27 ? MINV_F_FRAC.v[r][c] : MINV_G_FRAC.v[r][c]; }
+
+template <int Q>
+constexpr Inverse<Q> make_inverse() {
   Inverse<Q> out{};
   for (int r = 0; r < Q; ++r)
-    for (int c = 0; c < Q; ++c) out.v[r][c] = (float)A[r][Q + c].n / (float)A[r][Q + c].d;
+    for (int c = 0; c < Q; ++c) out.v[r][c] = (float)inverse_entry<Q>(r, c).n / (float)inverse_entry<Q>(r, c).d;
   return out;
 }
 constexpr Inverse<27> MINV_F = make_inverse<27>();
@@ -143,6 +159,90 @@ __device__ __forceinline__ void node_features(const C* d, const C* h, const Node
 }
 
 // ---------------------------------------------------------------------------
+// layout of the fused learned step: one node on two lanes of a wavefront
+// ---------------------------------------------------------------------------
+// In a 32x32x16 MFMA, lane (c, h) (c = lane % 32, h = lane / 32) supplies the
+// B operand rows k = 16 ks + 8 h + q and receives the result rows
+// 8 j + 4 h + q' (q' < 4) of each 32-row tile.  Storing logical row k of a
+// weight matrix at physical row perm_row(k) (bits 2 and 3 of k swapped) makes
+// the result registers of one layer, in order, the B operand of the next:
+// B[ks][q] = D[tile ks / 2][8 (ks % 2) + q].
+constexpr int perm_row(int k) { return (k & ~12) | ((k & 4) << 1) | ((k & 8) >> 1); }
+// result row of register r of tile mt in lane half h
+constexpr int d_row_of(int mt, int r, int h) { return 32 * mt + 8 * (r >> 2) + 4 * h + (r & 3); }
+// B-operand row (K index) of slot b (ks = b / 8, q = b % 8) in lane half h
+constexpr int slot_k(int h, int b) { return 16 * (b >> 3) + 8 * h + (b & 7); }
+
+// Populations owned by lane half h: slot s < 13 holds the f pair (2s + 1, 2s + 2),
+// half 0 the first and half 1 its opposite; slot 13 the f rest direction (half 0);
+// slots 14..22 the g pairs likewise; slot 23 the g rest direction (half 0).  -1
+// marks the two empty slots of half 1.  Global index: f_i = i, g_j = 27 + j.  The
+// two halves' directions at a slot are opposite, so one sign per lane turns the
+// half-0 direction into this lane's.
+constexpr int NSLOT = 24, NSLOT_F = 14;
+constexpr int owned_pop(int h, int s) {
+  if (s < NSLOT_F - 1) return 2 * s + 1 + h;
+  if (s == NSLOT_F - 1) return h ? -1 : 0;
+  if (s < NSLOT - 1) return 27 + 2 * (s - NSLOT_F) + 1 + h;
+  if (s == NSLOT - 1) return h ? -1 : 27;
+  return -1;
+}
+
+// BF16 bits of a dyadic rational num / den (den a power of two, |num| < 256): exact.
+constexpr uint16_t bf16_dyadic(long long num, long long den) {
+  if (num == 0) return 0;
+  const uint16_t sign = num < 0 ? 0x8000 : 0;
+  long long a = num < 0 ? -num : num;
+  int e = 0;                                         // value = a / den = m * 2^e, 1 <= m < 2
+  while (a >= 2 * den) { den *= 2; ++e; }
+  while (a < den) { a *= 2; --e; }
+  // mantissa: 7 bits of (a - den) / den
+  const long long frac = ((a - den) << 7) / den;
+  return (uint16_t)(sign | ((uint16_t)(e + 127) << 7) | (uint16_t)frac);
+}
+
+// Constant A operands of the fused step:
+//  feat: [physical row perm_row(k)][K index] = -(moment k of the owned population at
+//        that K index), k a non-conserved moment; features are M (f - f^eq) = -M d;
+//  minv: [result row of slot s of half h][output k] = M^-1 entry mapping the
+//        non-conserved moment correction dm_k onto population owned_pop(h, s).
+struct StepTables {
+  uint16_t feat[64 * K_IN];
+  uint16_t minv[64 * K_IN];
+};
+
+constexpr bool conserved_feature(int k) { return k < NCF || k == 27 || k >= N_IN - 1; }
+
+constexpr StepTables make_step_tables() {
+  StepTables t{};
+  for (int row = 0; row < 64; ++row) {
+    const int k = perm_row(row);
+    for (int kk = 0; kk < K_IN; ++kk) {
+      const int h = (kk >> 3) & 1, b = 8 * (kk >> 4) + (kk & 7);
+      const int p = owned_pop(h, b);
+      int v = 0;
+      if (p >= 0 && k < N_IN && !conserved_feature(k)) {
+        if (k < 27 && p < 27) v = -mom_entry<27>(k, p);
+        if (k >= 27 && p >= 27) v = -mom_entry<19>(k - 27, p - 27);
+      }
+      t.feat[row * K_IN + kk] = bf16_dyadic(v, 1);
+    }
+  }
+  const Frac zero{0, 1};
+  for (int row = 0; row < 64; ++row) {
+    const int mt = row >> 5, h = (row >> 2) & 1, r = 4 * ((row >> 3) & 3) + (row & 3);
+    const int p = owned_pop(h, 16 * mt + r);
+    for (int k = 0; k < K_IN; ++k) {
+      Frac v = zero;
+      if (p >= 0 && p < 27 && k < 27 - NCF) v = inverse_entry<27>(p, NCF + k);
+      if (p >= 27 && k >= 27 - NCF && k < N_OUT) v = inverse_entry<19>(p - 27, NCG + k - (27 - NCF));
+      t.minv[row * K_IN + k] = bf16_dyadic(v.n, v.d);
+    }
+  }
+  return t;
+}
+
+// ---------------------------------------------------------------------------
 // packed network (device): BF16 weights in MFMA-friendly row-major tiles,
 // FP32 biases and normalisation
 // ---------------------------------------------------------------------------
@@ -155,6 +255,12 @@ struct Packed {
   float b1[N_HID], b2[N_HID], b3[M_OUT];
   float x_mean[K_IN], x_iscale[K_IN], y_scale[M_OUT];
   float zero[M_OUT];                // a zero bias for the backward products
+  // the fused step's copies: rows at perm_row(logical row), W3 and b3 times y_scale
+  alignas(16) uint16_t w1p[64 * K_IN];
+  alignas(16) uint16_t w2p[64 * N_HID];
+  alignas(16) uint16_t w3p[64 * N_HID];
+  alignas(16) StepTables tab;
+  alignas(16) float b1p[64], b2p[64], b3p[64], x_mean_p[64], x_iscale_p[64];
 };
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
