@@ -170,6 +170,12 @@ def forms(stgv, stream, t_end, steps, warmup):
                                "bytes_per_node": bpn,
                                "hbm_frac": round(bpn * n ** 3 / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
     out["stencil_pairs_fp32"] = pairs
+    # the largest single-GPU case: 512^3, FP16 storage in place (12.35 GB), Re 3200, Fr 0.5
+    big = dict(n=512, q_f=27, q_g=19, storage="fp16", **dict(phys, re=3200.0, fr=0.5))
+    ms = kernel_time(stgv, stream, big, max(20, steps // 4), warmup)
+    out["large_512_fp16"] = {"kernel_ms": round(ms, 4), "mlups": round(512 ** 3 / (ms * 1e-3) / 1e6, 1),
+                             "bytes_per_node": 184,
+                             "hbm_frac": round(184 * 512 ** 3 / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
     net_path = os.path.join(ROOT, "paper_2605_14505_amd", "data", "learned64.npz")
     if os.path.exists(net_path):
         z = np.load(net_path, allow_pickle=False)

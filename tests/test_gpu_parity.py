@@ -360,3 +360,13 @@ def test_full_size_256_sampled_parity(forcing):
               g_over_n=1.0, noise_amp=1e-6, seed=0)
     for steps in (1, 2):
         _sampled_patch_parity(kw, steps, 24, tol=4e-6 * steps)
+
+
+def test_large_512_fp16_sampled_parity():
+    # the 512^3 single-GPU case: FP16 weight-shifted storage in the AA layout (12.35 GB),
+    # velocity shift, Re 3200, Fr 0.5.  Against the FP64 oracle the error is FP16 storage
+    # rounding: one rounding of the initial deviations and one per step, each at most
+    # 2^-11 of a deviation, so 3 * 2^-11 of the largest deviation after one step.
+    kw = dict(n=512, q_f=27, q_g=19, forcing="shift", storage="fp16", u0=0.05, re=3200.0, fr=0.5,
+              sc=0.7, g_over_n=0.02, noise_amp=1e-6, seed=0)
+    _sampled_patch_parity(kw, 1, 16, tol=3.0 * 2.0 ** -11)
