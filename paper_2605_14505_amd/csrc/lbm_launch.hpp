@@ -30,6 +30,9 @@ inline LaunchShape node_shape(int n) {
   } else if (n % 64 != 0 && n % 32 == 0) {
     bx = 32;                      // whole 128-byte lines per row, no idle lanes (n = 96, 160, ...)
     by = 8;
+  } else if (n % 64 == 0) {
+    bx = n % 256 == 0 ? 256 : (n % 128 == 0 ? 128 : 64);   // rows split evenly (n = 320, 384, 448)
+    by = 256 / bx;
   } else {
     bx = ((n + 63) / 64) * 64;
     if (bx > STGV_BLOCK_X) bx = STGV_BLOCK_X;

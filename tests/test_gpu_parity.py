@@ -354,6 +354,13 @@ def _sampled_patch_parity(kw, steps, count, tol):
     assert worst < tol
 
 
+def test_sampled_parity_with_64x4_blocks():
+    # n = 320: a multiple of 64 but not of 128 or 256 runs 64 x 4 node blocks
+    kw = dict(n=320, q_f=27, q_g=19, forcing="shift", u0=0.05, re=1600.0, fr=0.5, sc=0.7,
+              g_over_n=0.02, noise_amp=1e-6, seed=0)
+    _sampled_patch_parity(kw, 1, 12, tol=4e-6)
+
+
 @pytest.mark.parametrize("forcing", ["guo", "shift"])
 def test_full_size_256_sampled_parity(forcing):
     kw = dict(n=256, q_f=27, q_g=19, forcing=forcing, u0=0.05, re=1600.0, fr=1.0, sc=0.7,
