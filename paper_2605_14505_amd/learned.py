@@ -228,6 +228,53 @@ def coarse_run(nc, phys, t_end, diag_every, net=None, device="cuda:0"):
     return recs, steps, wall
 
 
+def guarded_run(nc, phys, t_end, diag_every, net, check_every=None, keep=4, device="cuda:0"):
+    """A learned coarse run with the plain step as its fallback.
+
+    The state is kept every `check_every` steps (default 10 diagnostic intervals; the
+    last `keep` states).  An interval is bad when one of its records is non-finite, has
+    max|u| above the lattice speed of sound, or has a total energy E_k + E_p above the
+    initial one by more than 1 % (the decaying flow has no energy source).  On the first
+    bad interval the run returns to the newest kept state, detaches the network and goes
+    on with the plain step; if the plain step fails too, it steps back to older kept
+    states.  Returns (records, step of the fallback or None)."""
+    steps = int(round(t_end * steps_per_unit_time(nc, phys["u0"])))
+    check_every = check_every or 10 * diag_every
+    sim = stgv.Simulation(device=device, n=nc, diag_every=diag_every, **phys)
+    if net is not None:
+        sim.set_mlp(net.packed)
+    sim.sample()
+    first = sim.diagnostics(raise_unstable=False)[0]
+    e0 = first["ek"] + first["ep"]
+    kept = [(0, sim.populations().clone(), [])]              # (step, state, records up to it)
+    recs, fallback, learned_on, done = [], None, net is not None, 0
+    while done < steps:
+        k = min(check_every, steps - done)
+        sim.step(k)
+        new, status = stgv.lbm_diagnostics(sim.ctx, raise_unstable=False)
+        bad = (status == stgv.LBM_EUNSTABLE
+               or any(r["nonfinite"] or not (r["ek"] + r["ep"] <= 1.01 * e0) for r in new))
+        if bad:
+            if learned_on:
+                sim.set_mlp(None)
+                learned_on = False
+            elif len(kept) > 1:
+                kept.pop()
+            else:
+                sim.close()
+                raise stgv.LbmError(stgv.LBM_EUNSTABLE, "the plain step is unstable from the initial state")
+            done, state, recs = kept[-1][0], kept[-1][1], list(kept[-1][2])
+            sim.load(state, step=done)
+            fallback = done
+            continue
+        recs.extend(new)
+        done += k
+        kept.append((done, sim.populations().clone(), list(recs)))
+        del kept[:-keep]
+    sim.close()
+    return recs, fallback
+
+
 SERIES = ("ek", "ep", "eps_k", "eps_p")
 
 
@@ -346,8 +393,9 @@ def pipeline(nc=64, train_fr=(0.3, 1.0, 3.0), seeds=(0,), test_fr=0.6, t_end=30.
 
     phys = physics(test_fr, 0)
     plain, steps_c, wall_plain = coarse_run(nc, phys, t_end, de_c, device=device)
-    learned, _, wall_learned = coarse_run(nc, phys, t_end, de_c, net=deployed or with_gain(net, 0.0),
-                                          device=device)
+    _, _, wall_learned = coarse_run(nc, phys, t_end, de_c, net=deployed or with_gain(net, 0.0), device=device)
+    # the deployed run, with the plain step as its fallback
+    learned, fallback = guarded_run(nc, phys, t_end, de_c, deployed, device=device)
     e_plain, e_learned = series_errors(plain, ref), series_errors(learned, ref)
     summary = {
         "workload": f"learned {nc}^3 vs plain {nc}^3 vs plain {RATIO * nc}^3 teacher, stratified TGV "
@@ -358,7 +406,7 @@ def pipeline(nc=64, train_fr=(0.3, 1.0, 3.0), seeds=(0,), test_fr=0.6, t_end=30.
         "one_step_ratio_test": losses["test_net"] / losses["test_zero"],
         "validation_score_by_gain": validation, "gain": best,
         "errors_plain": e_plain, "errors_learned": e_learned,
-        "score_plain": score(e_plain), "score_learned": score(e_learned),
+        "score_plain": score(e_plain), "score_learned": score(e_learned), "fallback_step": fallback,
         "coarse_steps": steps_c,
         "mlups_plain": nc3 * steps_c / wall_plain / 1e6,
         "mlups_learned": nc3 * steps_c / wall_learned / 1e6,

@@ -37,3 +37,25 @@ def test_trained_network_gain_over_the_plain_coarse_step():
     # 64^3 run at the unseen Froude number: E_k + E_p + -dE/dt errors against the teacher
     assert summary["gain"] > 0 and deployed is not None
     assert summary["score_learned"] < 0.75 * summary["score_plain"]
+
+
+def test_guarded_run_falls_back_to_the_plain_step():
+    # The shipped network (trained on Fr 0.3 / 1 / 3 to t = 30) applied at full gain
+    # drives the coarse run unstable within a few hundred steps; the guarded run returns
+    # to a kept state from which the plain step stays stable (stepping back further when the
+    # learned state had already gone bad) and finishes finite.  At gain 0 it never falls back.
+    import os
+    import numpy as np
+    path = os.path.join(os.path.dirname(learned.__file__), "data", "learned64.npz")
+    z = np.load(path, allow_pickle=False)
+    net = learned.Network(z["theta"], z["norm"])
+    phys = learned.physics(1.0)
+    de = 20
+    recs, fallback = learned.guarded_run(64, phys, 10.0, de, learned.with_gain(net, 1.0))
+    print(f"\nfull gain: fell back at step {fallback}, {len(recs)} records, last E_k {recs[-1]['ek']:.4e}")
+    assert fallback is not None
+    assert all(r["nonfinite"] == 0 and math.isfinite(r["ek"]) for r in recs)
+    steps = [r["step"] for r in recs]
+    assert steps == sorted(set(steps)) and steps[0] == 0 and steps[-1] >= 2000
+    recs0, fallback0 = learned.guarded_run(64, phys, 10.0, de, learned.with_gain(net, 0.0))
+    assert fallback0 is None and len(recs0) == len(recs)
