@@ -236,8 +236,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs the single-GPU step only: the halo-exchange path across GPUs is not "
-              "part of this build (use --gpus 1)", file=sys.stderr)
+        print("bench.py runs the single-GPU step only: the library has no halo exchange across "
+              "GPUs (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -6,7 +6,7 @@ Mach number) and is restricted again (b), and the coarse step of a gives c.  Eac
 node yields one training pair: its 47 features in a and the non-conserved moments of
 b - c returned to the node each population streamed from.  The network is trained on
 those pairs with the library's gradient and Adam kernels, then attached to a coarse run
-(the fused learned step) and judged against the fine run's energy and dissipation
+(the fused learned step) and compared with the fine run's energy and dissipation
 histories, next to the plain coarse run.
 
 Every numerical step runs in the library's kernels; this module allocates device
