@@ -2,8 +2,10 @@
 
     python -m paper_2605_14505_amd.build
 
-compiles every csrc/*.hip translation unit in parallel into _build/ and links
-paper_2605_14505_amd/lib/libstgv.so.  It always recompiles.
+compiles every csrc/*.hip translation unit in parallel into _build/, links
+paper_2605_14505_amd/lib/libstgv.so and the command-line driver
+paper_2605_14505_amd/bin/stgv_run (csrc/stgv_run.cpp, C ABI only).  It always
+recompiles.
 """
 import concurrent.futures as cf
 import os
@@ -16,6 +18,8 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libstgv.so")
+BINDIR = os.path.join(PKG, "bin")
+RUNNER = os.path.join(BINDIR, "stgv_run")
 ARCH = "gfx950"
 
 CFLAGS = [
@@ -57,8 +61,15 @@ def build(verbose=True):
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    os.makedirs(BINDIR, exist_ok=True)
+    cmd = [hipcc(), "-O2", "-std=c++17", "-Wall", os.path.join(CSRC, "stgv_run.cpp"), "-o", RUNNER + ".tmp",
+           f"-L{LIBDIR}", "-lstgv", "-Wl,-rpath,$ORIGIN/../lib"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"driver build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(RUNNER + ".tmp", RUNNER)
     if verbose:
-        print(f"built {LIB}", flush=True)
+        print(f"built {LIB} and {RUNNER}", flush=True)
     return LIB
 
 

@@ -1,0 +1,68 @@
+"""The command-line driver stgv_run (C ABI only, no Python in the loop): its argument and
+parameter errors on the CPU, and on the GPU the same diagnostic records as a run through
+the Python binding with the same parameters."""
+import os
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+RUNNER = os.path.join(ROOT, "paper_2605_14505_amd", "bin", "stgv_run")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(RUNNER), reason="stgv_run not built")
+
+
+def run(*args, timeout=60):
+    return subprocess.run([RUNNER, *map(str, args)], capture_output=True, text=True, timeout=timeout)
+
+
+def test_help_and_bad_options():
+    r = run("--help")
+    assert r.returncode == 0 and "usage" in r.stderr
+    for bad in (["--forcing", "foo"], ["--storage", "fp8"], ["--bogus", "1"], ["--n"], ["--steps", "-1"]):
+        r = run(*bad)
+        assert r.returncode == 2, bad
+        assert "usage" in r.stderr
+
+
+@pytest.mark.parametrize("args,msg", [
+    (["--n", "3"], "n = 3"),
+    (["--qf", "27", "--qg", "5"], "stencil pair"),
+    (["--storage", "fp16", "--compute", "fp64"], "LBM_EINVAL"),
+    (["--u0", "0.5"], "LBM_EINVAL"),
+])
+def test_parameter_errors_stop_before_the_gpu(args, msg):
+    # lbm_query_sizes validates on the CPU, so these never allocate device memory
+    r = run(*args)
+    assert r.returncode == 1
+    assert "parameters" in r.stderr and msg in r.stderr
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("forcing,storage", [("shift", "fp32"), ("guo", "fp16")])
+def test_driver_records_match_the_binding(forcing, storage):
+    import torch
+
+    from paper_2605_14505_amd import stgv
+
+    kw = dict(n=32, q_f=27, q_g=19, forcing=forcing, storage=storage, u0=0.05, re=400.0, fr=1.0, sc=0.7,
+              g_over_n=0.02, noise_amp=1e-6, seed=5, diag_every=25)
+    r = run("--n", 32, "--qf", 27, "--qg", 19, "--forcing", forcing, "--storage", storage, "--re", 400, "--fr", 1,
+            "--sc", 0.7, "--u0", 0.05, "--gn", 0.02, "--noise", 1e-6, "--seed", 5, "--steps", 200, "--diag", 25,
+            timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert "MLUPS" in r.stderr
+    lines = r.stdout.strip().splitlines()
+    assert lines[0] == "step,t,ek,ep,eps_k,eps_p,mass,umax"
+    rows = [list(map(float, ln.split(","))) for ln in lines[1:]]
+    sim = stgv.Simulation(device="cuda:0", **kw)
+    sim.step(200)
+    recs = sim.diagnostics()
+    sim.close()
+    torch.cuda.synchronize()
+    assert len(rows) == len(recs) == 8
+    for row, rec in zip(rows, recs):
+        assert int(row[0]) == rec["step"]
+        # same library, same kernels: equal up to the 11 significant digits printed
+        for j, key in enumerate(("ek", "ep", "eps_k", "eps_p", "mass"), start=2):
+            assert row[j] == pytest.approx(rec[key], rel=1e-10, abs=1e-300), (rec["step"], key)
