@@ -88,12 +88,6 @@ template <typename C> __device__ __forceinline__ C load_as(const bf16_t* p) {
   return (C)__uint_as_float(((uint32_t)get(&p->bits)) << 16);
 }
 
-__device__ __forceinline__ uint16_t float_to_bf16_rne(float v) {
-  uint32_t u = __float_as_uint(v);
-  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
 // Population stores bypass the caches by default (each value is read again only
 // one step later, after the whole ~GB state has streamed through).
 #ifndef STGV_NT_STORE
@@ -108,11 +102,14 @@ __device__ __forceinline__ void put(T* p, T v) {
 #endif
 }
 // Rounding to the storage type is round-to-nearest-even in every case (a double
-// is rounded once, straight to FP32; FP16 / BF16 stores take FP32 values).
+// is rounded once, straight to FP32; FP16 / BF16 stores take FP32 values, and
+// the BF16 conversion is gfx950's own, v_cvt_pk_bf16_f32).
 __device__ __forceinline__ void store_as(float* p, float v) { put(p, v); }
 __device__ __forceinline__ void store_as(float* p, double v) { put(p, (float)v); }
 __device__ __forceinline__ void store_as(_Float16* p, float v) { put(p, (_Float16)v); }
-__device__ __forceinline__ void store_as(bf16_t* p, float v) { put(&p->bits, float_to_bf16_rne(v)); }
+__device__ __forceinline__ void store_as(bf16_t* p, float v) {
+  put(&p->bits, __builtin_bit_cast(uint16_t, (__bf16)v));   // gfx950 converts in hardware
+}
 
 // ---------------------------------------------------------------------------
 // neighbour addressing on the periodic box
