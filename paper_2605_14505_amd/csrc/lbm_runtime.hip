@@ -20,98 +20,97 @@ namespace stgv {
 
 // ---------------------------------------------------------------------------
 // Dissipation stencil: eps_k needs |curl u|^2 and eps_p needs |grad rho'|^2 by
-// second-order central differences (periodic).  A 64 x 4 tile of x-y columns
-// marches up a chunk of z; each z-plane of the tile plus a one-node halo is
-// staged in LDS for the in-plane derivatives, and the z-neighbours of the own
-// column stay in registers.
+// second-order central differences (periodic).  One node per thread on the node
+// kernels' block shape (whole rows where n allows), one z-plane per grid row;
+// each thread loads the 14 neighbour values its derivatives use straight from
+// the field arrays and relies on the caches for the reuse.  Consecutive blocks
+// go to the 8 XCDs in turn, each with its own L2, so the blocks of a plane are
+// remapped to give every XCD a contiguous band of rows: the y-neighbour rows a
+// block reads are then, but for the band edges, read by blocks of the same XCD,
+// and the z-neighbour planes by the blocks of the same band one plane away,
+// which run at about the same time.
 // ---------------------------------------------------------------------------
-constexpr int FD_TX = 64, FD_TY = 4, FD_ZC = 32;
+constexpr int kXcds = 8;
 
 __global__ __launch_bounds__(256) void lbm_fd_kernel(const float* __restrict__ fields, int n,
                                                      double* __restrict__ partials) {
-  __shared__ float plane[4][FD_TY + 2][FD_TX + 2];     // u_x, u_y, u_z, rho'
-  const int64_t n2 = (int64_t)n * n, n3 = n2 * n;
-  const float* ux = fields + n3;
-  const float* uy = fields + 2 * n3;
-  const float* uz = fields + 3 * n3;
-  const float* rp = fields + 4 * n3;
-  const int tx = threadIdx.x, ty = threadIdx.y;
-  const int tid = tx + FD_TX * ty;
-  const int x0 = blockIdx.x * FD_TX, y0 = blockIdx.y * FD_TY;
-  const int x = x0 + tx, y = y0 + ty;
-  const bool active = (x < n) && (y < n);
-  const int z0 = blockIdx.z * FD_ZC;
-  const int z1 = min(z0 + FD_ZC, n);
-  const int64_t col = (int64_t)(active ? x : 0) + (int64_t)n * (active ? y : 0);
-
-  // own column at z - 1 and z
-  auto zwrap = [n](int z) { return z < 0 ? z + n : (z >= n ? z - n : z); };
-  float cx_m = ux[col + n2 * zwrap(z0 - 1)], cx_0 = ux[col + n2 * z0];
-  float cy_m = uy[col + n2 * zwrap(z0 - 1)], cy_0 = uy[col + n2 * z0];
-  float cr_m = rp[col + n2 * zwrap(z0 - 1)], cr_0 = rp[col + n2 * z0];
-  double curl2 = 0.0, grad2 = 0.0;
-
-  for (int z = z0; z < z1; ++z) {
-    const int64_t zoff = n2 * z;
-    __syncthreads();
-    for (int c = tid; c < (FD_TY + 2) * (FD_TX + 2); c += FD_TX * FD_TY) {
-      const int ly = c / (FD_TX + 2), lx = c % (FD_TX + 2);
-      const int gx = (x0 + lx - 1 + n) % n, gy = (y0 + ly - 1 + n) % n;
-      const int64_t a = zoff + gx + (int64_t)n * gy;
-      plane[0][ly][lx] = ux[a];
-      plane[1][ly][lx] = uy[a];
-      plane[2][ly][lx] = uz[a];
-      plane[3][ly][lx] = rp[a];
-    }
-    __syncthreads();
-    const int64_t zp = n2 * zwrap(z + 1);
-    const float cx_p = ux[col + zp], cy_p = uy[col + zp], cr_p = rp[col + zp];
-    if (active) {
-      const int lx = tx + 1, ly = ty + 1;
-      const float duz_dx = 0.5f * (plane[2][ly][lx + 1] - plane[2][ly][lx - 1]);
-      const float duz_dy = 0.5f * (plane[2][ly + 1][lx] - plane[2][ly - 1][lx]);
-      const float duy_dx = 0.5f * (plane[1][ly][lx + 1] - plane[1][ly][lx - 1]);
-      const float dux_dy = 0.5f * (plane[0][ly + 1][lx] - plane[0][ly - 1][lx]);
-      const float dux_dz = 0.5f * (cx_p - cx_m);
-      const float duy_dz = 0.5f * (cy_p - cy_m);
-      const float wx = duz_dy - duy_dz, wy = dux_dz - duz_dx, wz = duy_dx - dux_dy;
-      curl2 += (double)(wx * wx + wy * wy + wz * wz);
-      const float gx = 0.5f * (plane[3][ly][lx + 1] - plane[3][ly][lx - 1]);
-      const float gy = 0.5f * (plane[3][ly + 1][lx] - plane[3][ly - 1][lx]);
-      const float gz = 0.5f * (cr_p - cr_m);
-      grad2 += (double)(gx * gx + gy * gy + gz * gz);
-    }
-    cx_m = cx_0; cx_0 = cx_p;
-    cy_m = cy_0; cy_0 = cy_p;
-    cr_m = cr_0; cr_0 = cr_p;
+  int tx = blockIdx.x, ty = blockIdx.y;
+  if (gridDim.y % kXcds == 0) {            // the plane's blocks, in dispatch order, by XCD
+    const int lin = blockIdx.x + gridDim.x * blockIdx.y;
+    const int xcd = lin % kXcds, j = lin / kXcds;
+    ty = xcd * (gridDim.y / kXcds) + j / gridDim.x;
+    tx = j % gridDim.x;
   }
-  const double v[NFD] = {curl2, grad2};
+  const int x = tx * blockDim.x + threadIdx.x, y = ty * blockDim.y + threadIdx.y, z = blockIdx.z;
+  double v[NFD] = {0.0, 0.0};
+  if (x < n && y < n) {
+    const NodeIndex ix = make_index(x, y, z, n);
+    const size_t n3 = (size_t)n * n * n;
+    const float* ux = fields + n3;
+    const float* uy = fields + 2 * n3;
+    const float* uz = fields + 3 * n3;
+    const float* rp = fields + 4 * n3;
+    const float duz_dy = 0.5f * (uz[ix.at(0, 1, 0)] - uz[ix.at(0, -1, 0)]);
+    const float duy_dz = 0.5f * (uy[ix.at(0, 0, 1)] - uy[ix.at(0, 0, -1)]);
+    const float dux_dz = 0.5f * (ux[ix.at(0, 0, 1)] - ux[ix.at(0, 0, -1)]);
+    const float duz_dx = 0.5f * (uz[ix.at(1, 0, 0)] - uz[ix.at(-1, 0, 0)]);
+    const float duy_dx = 0.5f * (uy[ix.at(1, 0, 0)] - uy[ix.at(-1, 0, 0)]);
+    const float dux_dy = 0.5f * (ux[ix.at(0, 1, 0)] - ux[ix.at(0, -1, 0)]);
+    const float wx = duz_dy - duy_dz, wy = dux_dz - duz_dx, wz = duy_dx - dux_dy;
+    v[FD_CURL2] = (double)(wx * wx + wy * wy + wz * wz);
+    const float gx = 0.5f * (rp[ix.at(1, 0, 0)] - rp[ix.at(-1, 0, 0)]);
+    const float gy = 0.5f * (rp[ix.at(0, 1, 0)] - rp[ix.at(0, -1, 0)]);
+    const float gz = 0.5f * (rp[ix.at(0, 0, 1)] - rp[ix.at(0, 0, -1)]);
+    v[FD_GRAD2] = (double)(gx * gx + gy * gy + gz * gz);
+  }
+  // partials in dispatch order, so the reduction order does not depend on the remap
   const int64_t blk = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
   block_reduce_store<NFD, 0u>(v, partials + blk * NFD);
 }
 
 // ---------------------------------------------------------------------------
-// Final fixed-order FP64 reduction of the per-block partials into one record.
-// One block of 256 threads.
+// Fixed-order FP64 reduction of the per-block partials into one record, in two
+// launches: kMidBlocks blocks each reduce an even share of the step and stencil
+// partials into one row of NPART + NFD values, then one block reduces the rows
+// and writes the record.  Both orders depend only on the box size, so records
+// are bitwise reproducible.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void lbm_final_kernel(const double* __restrict__ sp, int64_t nsp,
-                                                        const double* __restrict__ fp, int64_t nfp,
+constexpr int kMidBlocks = 256;
+constexpr int kNV = NPART + NFD;
+constexpr unsigned kMaxMask = 1u << P_UMAX2;
+
+__global__ __launch_bounds__(256) void lbm_mid_kernel(const double* __restrict__ sp, int64_t nsp,
+                                                      const double* __restrict__ fp, int64_t nfp,
+                                                      double* __restrict__ mid) {
+  const int64_t b = blockIdx.x, nb = gridDim.x;
+  double v[kNV];
+#pragma unroll
+  for (int k = 0; k < kNV; ++k) v[k] = 0.0;
+  for (int64_t i = nsp * b / nb + threadIdx.x; i < nsp * (b + 1) / nb; i += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < NPART; ++k)
+      v[k] = ((kMaxMask >> k) & 1u) ? fmax(v[k], sp[i * NPART + k]) : v[k] + sp[i * NPART + k];
+  }
+  for (int64_t i = nfp * b / nb + threadIdx.x; i < nfp * (b + 1) / nb; i += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < NFD; ++k) v[NPART + k] += fp[i * NFD + k];
+  }
+  block_reduce_store<kNV, kMaxMask>(v, mid + b * kNV);
+}
+
+__global__ __launch_bounds__(256) void lbm_final_kernel(const double* __restrict__ mid, int64_t rows,
                                                         double* __restrict__ rec, int64_t step) {
-  constexpr int NV = NPART + NFD;
+  constexpr int NV = kNV;
   double v[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) v[k] = 0.0;
-  for (int64_t b = threadIdx.x; b < nsp; b += blockDim.x) {
+  for (int64_t b = threadIdx.x; b < rows; b += blockDim.x) {
 #pragma unroll
-    for (int k = 0; k < NPART; ++k)
-      v[k] = (k == P_UMAX2) ? fmax(v[k], sp[b * NPART + k]) : v[k] + sp[b * NPART + k];
-  }
-  for (int64_t b = threadIdx.x; b < nfp; b += blockDim.x) {
-#pragma unroll
-    for (int k = 0; k < NFD; ++k) v[NPART + k] += fp[b * NFD + k];
+    for (int k = 0; k < NV; ++k)
+      v[k] = ((kMaxMask >> k) & 1u) ? fmax(v[k], mid[b * NV + k]) : v[k] + mid[b * NV + k];
   }
   __shared__ double out[NV];
-  block_reduce_store<NV, (1u << P_UMAX2)>(v, out);
+  block_reduce_store<NV, kMaxMask>(v, out);
   __syncthreads();
   if (threadIdx.x == 0) {
     double r[NREC] = {0};
@@ -283,7 +282,7 @@ int derive(const lbm_params* p, Derived* d, char* err) {
 struct Sizes {
   int64_t n3, stride;
   size_t elem, pop_bytes;
-  size_t off_fields, off_sp, off_fp, off_ring, work_bytes;
+  size_t off_fields, off_sp, off_fp, off_mid, off_ring, work_bytes;
   int64_t nsp, nfp, nsp_learned;
 };
 
@@ -306,11 +305,12 @@ Sizes sizes_of(const lbm_params* p) {
   // the learned step runs 256-thread blocks of 128 nodes
   s.nsp_learned = (p->n % 64 == 0) ? (int64_t)p->n * p->n * p->n / 128 : 0;
   const int64_t nsp_max = s.nsp > s.nsp_learned ? s.nsp : s.nsp_learned;
-  s.nfp = (int64_t)((p->n + FD_TX - 1) / FD_TX) * ((p->n + FD_TY - 1) / FD_TY) * ((p->n + FD_ZC - 1) / FD_ZC);
+  s.nfp = s.nsp;                      // the stencil runs on the node kernels' shape
   size_t off = 0;
   s.off_fields = off; off = align_up(off + (size_t)(5 * s.n3) * sizeof(float), kAlign);
   s.off_sp = off;     off = align_up(off + (size_t)(nsp_max * NPART) * sizeof(double), kAlign);
   s.off_fp = off;     off = align_up(off + (size_t)(s.nfp * NFD) * sizeof(double), kAlign);
+  s.off_mid = off;    off = align_up(off + (size_t)kMidBlocks * kNV * sizeof(double), kAlign);
   s.off_ring = off;   off = align_up(off + (size_t)kRingCap * NREC * sizeof(double), kAlign);
   s.work_bytes = off;
   return s;
@@ -361,6 +361,7 @@ hipError_t launch_node(lbm_ctx* c, int mode, int flags, char* src, char* dst, fl
 float* fields_buf(lbm_ctx* c) { return (float*)(c->work + c->sz.off_fields); }
 double* sp_buf(lbm_ctx* c) { return (double*)(c->work + c->sz.off_sp); }
 double* fp_buf(lbm_ctx* c) { return (double*)(c->work + c->sz.off_fp); }
+double* mid_buf(lbm_ctx* c) { return (double*)(c->work + c->sz.off_mid); }
 double* ring_buf(lbm_ctx* c) { return (double*)(c->work + c->sz.off_ring); }
 
 // Layout of the current state for the gather of a moment-only pass.
@@ -374,15 +375,17 @@ char* current_array(const lbm_ctx* c) {
 
 // Queue the dissipation stencil and the final reduction into the next ring slot.
 hipError_t queue_record(lbm_ctx* c, int64_t step, bool learned) {
-  const dim3 fblock(FD_TX, FD_TY, 1);
-  const dim3 fgrid((c->p.n + FD_TX - 1) / FD_TX, (c->p.n + FD_TY - 1) / FD_TY,
-                   (c->p.n + FD_ZC - 1) / FD_ZC);
-  hipLaunchKernelGGL(lbm_fd_kernel, fgrid, fblock, 0, c->stream, fields_buf(c), c->p.n, fp_buf(c));
+  hipLaunchKernelGGL(lbm_fd_kernel, c->sh.grid, c->sh.block, 0, c->stream, fields_buf(c), c->p.n,
+                     fp_buf(c));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   double* slot = ring_buf(c) + (c->ring_head % kRingCap) * NREC;
-  hipLaunchKernelGGL(lbm_final_kernel, dim3(1), dim3(256), 0, c->stream, sp_buf(c),
-                     learned ? c->sz.nsp_learned : c->sz.nsp, fp_buf(c), c->sz.nfp, slot, step);
+  hipLaunchKernelGGL(lbm_mid_kernel, dim3(kMidBlocks), dim3(256), 0, c->stream, sp_buf(c),
+                     learned ? c->sz.nsp_learned : c->sz.nsp, fp_buf(c), c->sz.nfp, mid_buf(c));
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(lbm_final_kernel, dim3(1), dim3(256), 0, c->stream, mid_buf(c),
+                     (int64_t)kMidBlocks, slot, step);
   e = hipGetLastError();
   if (e == hipSuccess) c->ring_head++;
   return e;
