@@ -20,50 +20,114 @@ namespace stgv {
 
 // ---------------------------------------------------------------------------
 // Dissipation stencil: eps_k needs |curl u|^2 and eps_p needs |grad rho'|^2 by
-// second-order central differences (periodic).  One node per thread on the node
-// kernels' block shape (whole rows where n allows), one z-plane per grid row;
-// each thread loads the 14 neighbour values its derivatives use straight from
-// the field arrays and relies on the caches for the reuse.  Consecutive blocks
-// go to the 8 XCDs in turn, each with its own L2, so the blocks of a plane are
-// remapped to give every XCD a contiguous band of rows: the y-neighbour rows a
-// block reads are then, but for the band edges, read by blocks of the same XCD,
-// and the z-neighbour planes by the blocks of the same band one plane away,
-// which run at about the same time.
+// second-order central differences (periodic).  A 64 x 4 tile of x-y columns
+// marches up a chunk of z.  Each z-plane of the tile plus a one-node halo is
+// staged in LDS (double-buffered, one barrier per plane) for the in-plane
+// derivatives while the next plane is already on its way into registers; the
+// z-derivatives of a plane are taken one plane later, when the plane above has
+// arrived, from the column's values kept in registers.  Node by node, the
+// arithmetic and the order of each thread's sum (planes z0, z0 + 1, ...) are
+// those of the plain definition.
+//
+// The hardware hands consecutive blocks to the 8 XCDs in turn, each with its own
+// L2; left so, a tile's halo rows belong to tiles on other XCDs and are fetched
+// from HBM again.  The tiles of a z-chunk are therefore remapped so that every
+// XCD owns a contiguous band of rows, whose inner halos its own L2 then serves.
 // ---------------------------------------------------------------------------
+#ifndef STGV_FD_ZC
+#define STGV_FD_ZC 32
+#endif
+constexpr int FD_TX = 64, FD_TY = 4, FD_ZC = STGV_FD_ZC;
+constexpr int FD_W = FD_TX + 2, FD_H = FD_TY + 2;
+constexpr int FD_CELLS = FD_W * FD_H;
+constexpr int FD_SLOTS = (FD_CELLS + FD_TX * FD_TY - 1) / (FD_TX * FD_TY);
 constexpr int kXcds = 8;
 
 __global__ __launch_bounds__(256) void lbm_fd_kernel(const float* __restrict__ fields, int n,
                                                      double* __restrict__ partials) {
-  int tx = blockIdx.x, ty = blockIdx.y;
-  if (gridDim.y % kXcds == 0) {            // the plane's blocks, in dispatch order, by XCD
+  __shared__ float plane[2][4][FD_H][FD_W];     // u_x, u_y, u_z, rho'
+  const int64_t n2 = (int64_t)n * n, n3 = n2 * n;
+  const float* ux = fields + n3;
+  const float* uy = fields + 2 * n3;
+  const float* uz = fields + 3 * n3;
+  const float* rp = fields + 4 * n3;
+  int bx = blockIdx.x, by = blockIdx.y;
+  if (gridDim.y % kXcds == 0) {            // the chunk's tiles, in dispatch order, by XCD
     const int lin = blockIdx.x + gridDim.x * blockIdx.y;
     const int xcd = lin % kXcds, j = lin / kXcds;
-    ty = xcd * (gridDim.y / kXcds) + j / gridDim.x;
-    tx = j % gridDim.x;
+    by = xcd * (gridDim.y / kXcds) + j / gridDim.x;
+    bx = j % gridDim.x;
   }
-  const int x = tx * blockDim.x + threadIdx.x, y = ty * blockDim.y + threadIdx.y, z = blockIdx.z;
-  double v[NFD] = {0.0, 0.0};
-  if (x < n && y < n) {
-    const NodeIndex ix = make_index(x, y, z, n);
-    const size_t n3 = (size_t)n * n * n;
-    const float* ux = fields + n3;
-    const float* uy = fields + 2 * n3;
-    const float* uz = fields + 3 * n3;
-    const float* rp = fields + 4 * n3;
-    const float duz_dy = 0.5f * (uz[ix.at(0, 1, 0)] - uz[ix.at(0, -1, 0)]);
-    const float duy_dz = 0.5f * (uy[ix.at(0, 0, 1)] - uy[ix.at(0, 0, -1)]);
-    const float dux_dz = 0.5f * (ux[ix.at(0, 0, 1)] - ux[ix.at(0, 0, -1)]);
-    const float duz_dx = 0.5f * (uz[ix.at(1, 0, 0)] - uz[ix.at(-1, 0, 0)]);
-    const float duy_dx = 0.5f * (uy[ix.at(1, 0, 0)] - uy[ix.at(-1, 0, 0)]);
-    const float dux_dy = 0.5f * (ux[ix.at(0, 1, 0)] - ux[ix.at(0, -1, 0)]);
-    const float wx = duz_dy - duy_dz, wy = dux_dz - duz_dx, wz = duy_dx - dux_dy;
-    v[FD_CURL2] = (double)(wx * wx + wy * wy + wz * wz);
-    const float gx = 0.5f * (rp[ix.at(1, 0, 0)] - rp[ix.at(-1, 0, 0)]);
-    const float gy = 0.5f * (rp[ix.at(0, 1, 0)] - rp[ix.at(0, -1, 0)]);
-    const float gz = 0.5f * (rp[ix.at(0, 0, 1)] - rp[ix.at(0, 0, -1)]);
-    v[FD_GRAD2] = (double)(gx * gx + gy * gy + gz * gz);
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int tid = tx + FD_TX * ty;
+  const int x0 = bx * FD_TX, y0 = by * FD_TY;
+  const bool active = (x0 + tx < n) && (y0 + ty < n);
+  const int z0 = blockIdx.z * FD_ZC;
+  const int z1 = min(z0 + FD_ZC, n);
+  auto zwrap = [n](int z) { return z < 0 ? z + n : (z >= n ? z - n : z); };
+
+  // this thread's cells of the staged tile and their in-plane offsets, wrapped once
+  int64_t off[FD_SLOTS];
+  int cell[FD_SLOTS];
+#pragma unroll
+  for (int s = 0; s < FD_SLOTS; ++s) {
+    const int c = tid + FD_TX * FD_TY * s;
+    cell[s] = c < FD_CELLS ? c : -1;
+    const int ly = c / FD_W, lx = c % FD_W;
+    const int gx = ((x0 + lx - 1) % n + n) % n, gy = ((y0 + ly - 1) % n + n) % n;
+    off[s] = c < FD_CELLS ? gx + (int64_t)n * gy : 0;
+  }
+  float r[FD_SLOTS][4];
+  auto fetch = [&](int z) {
+    const int64_t zo = n2 * zwrap(z);
+#pragma unroll
+    for (int s = 0; s < FD_SLOTS; ++s) {
+      if (cell[s] < 0) continue;
+      r[s][0] = ux[zo + off[s]];
+      r[s][1] = uy[zo + off[s]];
+      r[s][2] = uz[zo + off[s]];
+      r[s][3] = rp[zo + off[s]];
+    }
+  };
+
+  // per column: centres of the two planes below, in-plane terms of the plane below
+  float cx_2 = 0.f, cy_2 = 0.f, cr_2 = 0.f, cx_1 = 0.f, cy_1 = 0.f, cr_1 = 0.f;
+  float duz_dy = 0.f, duz_dx = 0.f, duy_dx = 0.f, dux_dy = 0.f, gx = 0.f, gy = 0.f;
+  double curl2 = 0.0, grad2 = 0.0;
+  const int lx = tx + 1, ly = ty + 1;
+
+  fetch(z0 - 1);
+  for (int z = z0 - 1; z <= z1; ++z) {
+    const int b = (z - z0 + 1) & 1;
+#pragma unroll
+    for (int s = 0; s < FD_SLOTS; ++s) {
+      if (cell[s] < 0) continue;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) (&plane[b][f][0][0])[cell[s]] = r[s][f];
+    }
+    if (z < z1) fetch(z + 1);
+    __syncthreads();
+    const float cx_0 = plane[b][0][ly][lx], cy_0 = plane[b][1][ly][lx], cr_0 = plane[b][3][ly][lx];
+    if (active && z >= z0 + 1) {          // plane z - 1 is complete
+      const float dux_dz = 0.5f * (cx_0 - cx_2);
+      const float duy_dz = 0.5f * (cy_0 - cy_2);
+      const float wx = duz_dy - duy_dz, wy = dux_dz - duz_dx, wz = duy_dx - dux_dy;
+      curl2 += (double)(wx * wx + wy * wy + wz * wz);
+      const float gz = 0.5f * (cr_0 - cr_2);
+      grad2 += (double)(gx * gx + gy * gy + gz * gz);
+    }
+    // in-plane terms of plane z, used when plane z + 1 arrives
+    duz_dx = 0.5f * (plane[b][2][ly][lx + 1] - plane[b][2][ly][lx - 1]);
+    duz_dy = 0.5f * (plane[b][2][ly + 1][lx] - plane[b][2][ly - 1][lx]);
+    duy_dx = 0.5f * (plane[b][1][ly][lx + 1] - plane[b][1][ly][lx - 1]);
+    dux_dy = 0.5f * (plane[b][0][ly + 1][lx] - plane[b][0][ly - 1][lx]);
+    gx = 0.5f * (plane[b][3][ly][lx + 1] - plane[b][3][ly][lx - 1]);
+    gy = 0.5f * (plane[b][3][ly + 1][lx] - plane[b][3][ly - 1][lx]);
+    cx_2 = cx_1; cy_2 = cy_1; cr_2 = cr_1;
+    cx_1 = cx_0; cy_1 = cy_0; cr_1 = cr_0;
   }
   // partials in dispatch order, so the reduction order does not depend on the remap
+  const double v[NFD] = {curl2, grad2};
   const int64_t blk = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
   block_reduce_store<NFD, 0u>(v, partials + blk * NFD);
 }
@@ -305,7 +369,7 @@ Sizes sizes_of(const lbm_params* p) {
   // the learned step runs 256-thread blocks of 128 nodes
   s.nsp_learned = (p->n % 64 == 0) ? (int64_t)p->n * p->n * p->n / 128 : 0;
   const int64_t nsp_max = s.nsp > s.nsp_learned ? s.nsp : s.nsp_learned;
-  s.nfp = s.nsp;                      // the stencil runs on the node kernels' shape
+  s.nfp = (int64_t)((p->n + FD_TX - 1) / FD_TX) * ((p->n + FD_TY - 1) / FD_TY) * ((p->n + FD_ZC - 1) / FD_ZC);
   size_t off = 0;
   s.off_fields = off; off = align_up(off + (size_t)(5 * s.n3) * sizeof(float), kAlign);
   s.off_sp = off;     off = align_up(off + (size_t)(nsp_max * NPART) * sizeof(double), kAlign);
@@ -375,8 +439,10 @@ char* current_array(const lbm_ctx* c) {
 
 // Queue the dissipation stencil and the final reduction into the next ring slot.
 hipError_t queue_record(lbm_ctx* c, int64_t step, bool learned) {
-  hipLaunchKernelGGL(lbm_fd_kernel, c->sh.grid, c->sh.block, 0, c->stream, fields_buf(c), c->p.n,
-                     fp_buf(c));
+  const dim3 fblock(FD_TX, FD_TY, 1);
+  const dim3 fgrid((c->p.n + FD_TX - 1) / FD_TX, (c->p.n + FD_TY - 1) / FD_TY,
+                   (c->p.n + FD_ZC - 1) / FD_ZC);
+  hipLaunchKernelGGL(lbm_fd_kernel, fgrid, fblock, 0, c->stream, fields_buf(c), c->p.n, fp_buf(c));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   double* slot = ring_buf(c) + (c->ring_head % kRingCap) * NREC;
