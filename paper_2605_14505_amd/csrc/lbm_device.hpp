@@ -194,6 +194,86 @@ __device__ __forceinline__ void scatter(const C* v, T* dst, int first, const Nod
 }
 
 // ---------------------------------------------------------------------------
+// x-staged push of the odd step (2-byte storage, blocks that hold part of a row)
+//
+// The odd step's push along e_x = +-1 moves a wavefront's 64 consecutive values
+// one element sideways, so each of its stores straddles a line boundary and
+// every line is completed by two wavefronts.  Staged, each lane first leaves
+// its rounded values of the directions with e_x != 0 in LDS at its own place
+// in the block; after one barrier lane x stores, at its own x, what lane
+// x - e_x left there, so the stores of a wavefront cover whole aligned lines.
+// The lanes at the block's x edges store their own value across the edge
+// directly, and the lane whose source sits in the neighbouring block stores
+// nothing for that direction: every destination is written exactly once, and
+// every location is still written after the barrier that follows its read.
+// ---------------------------------------------------------------------------
+template <int Q>
+constexpr int x_moving() {
+  int k = 0;
+  for (int i = 0; i < Q; ++i) k += Stencil<Q>::ex[i] != 0;
+  return k;
+}
+
+__device__ __forceinline__ _Float16 rounded(const _Float16*, float v) { return (_Float16)v; }
+__device__ __forceinline__ bf16_t rounded(const bf16_t*, float v) {
+  return bf16_t{__builtin_bit_cast(uint16_t, (__bf16)v)};
+}
+__device__ __forceinline__ void put_rounded(_Float16* p, _Float16 v) { put(p, v); }
+__device__ __forceinline__ void put_rounded(bf16_t* p, bf16_t v) { put(&p->bits, v.bits); }
+
+struct XLane {
+  int lid;           // thread index in the block (row-major over x, y)
+  int from_m;        // LDS place of the x - 1 neighbour (the lane's own at the block's left edge)
+  int from_p;        // ... of the x + 1 neighbour (own at the right edge)
+  bool left;         // first lane of its block row
+  bool right;        // last lane of its block row
+};
+
+__device__ __forceinline__ XLane make_xlane() {
+  const int tx = threadIdx.x, bx = blockDim.x;
+  XLane l;
+  l.left = tx == 0;
+  l.right = tx == bx - 1;
+  l.lid = threadIdx.y * bx + tx;
+  l.from_m = l.left ? l.lid : l.lid - 1;
+  l.from_p = l.right ? l.lid : l.lid + 1;
+  return l;
+}
+
+// Leave the rounded values of the directions with e_x != 0 in xs[k][lid].
+template <int Q, typename T, typename C>
+__device__ __forceinline__ void stage_x(const C* v, T (*xs)[256], int k0, const XLane& l) {
+  using S = Stencil<Q>;
+  int k = k0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    if (S::ex[i] == 0) continue;
+    xs[k++][l.lid] = rounded((const T*)nullptr, v[i]);
+  }
+}
+
+// The odd step's push (slot i at x + e_i) with the x-shift taken from LDS.
+template <int Q, typename T, typename C>
+__device__ __forceinline__ void scatter_staged(const C* v, T* dst, int first, const NodeIndex& ix,
+                                               int64_t stride, const T (*xs)[256], int k0,
+                                               const XLane& l) {
+  using S = Stencil<Q>;
+  int k = k0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    T* arr = dst + (int64_t)(first + i) * stride;
+    if (S::ex[i] == 0) {
+      store_as(at_node(arr, ix.at(0, S::ey[i], S::ez[i])), v[i]);
+      continue;
+    }
+    const bool plus = S::ex[i] > 0;
+    const T got = xs[k++][plus ? l.from_m : l.from_p];
+    if (!(plus ? l.left : l.right)) put_rounded(at_node(arr, ix.at(0, S::ey[i], S::ez[i])), got);
+    if (plus ? l.right : l.left) store_as(at_node(arr, ix.at(S::ex[i], S::ey[i], S::ez[i])), v[i]);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // node-local physics
 // ---------------------------------------------------------------------------
 // Moments over a lattice whose directions come in opposite pairs (i, i + 1):

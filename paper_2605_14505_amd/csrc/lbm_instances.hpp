@@ -29,6 +29,13 @@ hipError_t step_force(int mode, bool diag, const LaunchShape& sh, hipStream_t st
   return diag ? go_step<QF, QG, FORCE, T, M, STEP_DIAG>(sh, st, pop, dst, geo, c, fields, partials) \
               : go_step<QF, QG, FORCE, T, M, STEP>(sh, st, pop, dst, geo, c, fields, partials)
   if (mode == MODE_EVEN) STGV_GO(MODE_EVEN);
+  if constexpr (sizeof(T) == 2) {
+    if (mode == MODE_ODD && !diag && xstaged_shape(sh, geo.n)) {
+      hipLaunchKernelGGL((lbm_step_xstaged_kernel<QF, QG, FORCE, T, STGV_C>), sh.grid, sh.block, 0, st,
+                         pop, geo, c);
+      return hipGetLastError();
+    }
+  }
   if (mode == MODE_ODD) STGV_GO(MODE_ODD);
   if (mode == MODE_AB) STGV_GO(MODE_AB);
 #undef STGV_GO

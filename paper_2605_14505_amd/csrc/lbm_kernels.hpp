@@ -59,6 +59,31 @@ __global__ STGV_STEP_BOUNDS void lbm_step_kernel(T* pop, T* dst, Geometry geo,
   }
 }
 
+// The plain odd step with its x-shifted stores staged through LDS (scatter_staged).
+// Launched only for 2-byte storage on block shapes that tile the box exactly and
+// hold part of a row, so every lane is active and reaches the barrier.
+template <int QF, int QG, int FORCE, typename T, typename C>
+__global__ STGV_STEP_BOUNDS void lbm_step_xstaged_kernel(T* pop, Geometry geo, PhysConsts c) {
+  constexpr int KF = x_moving<QF>(), KG = x_moving<QG>();
+  __shared__ T xs[KF + KG][256];
+  const int n = geo.n;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const NodeIndex ix = make_index(x, y, blockIdx.z, n);
+  C f[QF], g[QG];
+  gather<QF, T, MODE_ODD>(f, pop, 0, ix, geo.stride);
+  gather<QG, T, MODE_ODD>(g, pop, QF, ix, geo.stride);
+  NodeMacro<C> m;
+  node_macro<QF, QG, FORCE>(f, g, c, m);
+  node_collide<QF, QG, FORCE>(f, g, c, m);
+  const XLane l = make_xlane();
+  stage_x<QF>(f, xs, 0, l);
+  stage_x<QG>(g, xs, KF, l);
+  __syncthreads();
+  scatter_staged<QF>(f, pop, 0, ix, geo.stride, xs, 0, l);
+  scatter_staged<QG>(g, pop, QF, ix, geo.stride, xs, KF, l);
+}
+
 // ---------------------------------------------------------------------------
 // Taylor-Green initial state (Eqs. (20)-(21)) in natural order.
 // ---------------------------------------------------------------------------

@@ -44,6 +44,20 @@ inline LaunchShape node_shape(int n) {
   return s;
 }
 
+// Whether the odd step of 2-byte storage stages its x-shifted stores through LDS
+// (lbm_step_xstaged_kernel): where 256-node blocks tile the box exactly and hold
+// part of a row, on boxes of at least STGV_XSTAGE_MIN_N a side.  Measured on
+// gfx950 (FP16 / BF16 odd step): 512^3 6.50 -> 5.77 ms and 6.41 -> 5.84 ms; with
+// 64- or 128-node blocks (320^3 - 448^3) and with whole rows in a block (256^3)
+// staging was slower, so those keep the plain push.
+#ifndef STGV_XSTAGE_MIN_N
+#define STGV_XSTAGE_MIN_N 512
+#endif
+inline bool xstaged_shape(const LaunchShape& sh, int n) {
+  const int bx = (int)sh.block.x, by = (int)sh.block.y;
+  return n >= STGV_XSTAGE_MIN_N && bx == 256 && by == 1 && n % bx == 0 && bx < n;
+}
+
 // Every function returns the launch error (hipSuccess when queued).
 template <typename T, typename C>
 hipError_t launch_step(int qf, int qg, int force, int mode, int flags, const LaunchShape& sh,

@@ -410,6 +410,28 @@ def test_large_512_fp16_sampled_parity():
     # velocity shift, Re 3200, Fr 0.5.  Against the FP64 oracle the error is FP16 storage
     # rounding: one rounding of the initial deviations and one per step, each at most
     # 2^-11 of a deviation, so 3 * 2^-11 of the largest deviation after one step.
+    # Each further step adds at most one more rounding; step 2 is an odd step, whose
+    # x-shifted stores go through LDS at this size (lbm_step_xstaged_kernel).
     kw = dict(n=512, q_f=27, q_g=19, forcing="shift", storage="fp16", u0=0.05, re=3200.0, fr=0.5,
               sc=0.7, g_over_n=0.02, noise_amp=1e-6, seed=0)
-    _sampled_patch_parity(kw, 1, 16, tol=3.0 * 2.0 ** -11)
+    for steps in (1, 2):
+        _sampled_patch_parity(kw, steps, 16, tol=(steps + 2) * 2.0 ** -11)
+
+
+@pytest.mark.parametrize("storage", ["fp16", "bf16"])
+def test_large_512_staged_odd_step_equals_ab_push(storage):
+    # At 512^3 the odd AA step of 2-byte storage stages its x-shifted stores through
+    # LDS; the A-B push does not.  Both store the same rounded values at the same
+    # places, so the states agree bit for bit after odd and even step counts.
+    kw = dict(n=512, q_f=27, q_g=19, forcing="shift", storage=storage, u0=0.05, re=3200.0,
+              fr=0.5, sc=0.7, g_over_n=0.02, noise_amp=1e-6, seed=0)
+    aa = gpu_sim(layout="aa", **kw)
+    ab = gpu_sim(layout="ab", **kw)
+    for k in (1, 1, 1):               # after steps 1, 2, 3
+        aa.step(k)
+        ab.step(k)
+        for a, b in zip(aa.populations().split(8), ab.populations().split(8)):
+            assert torch.equal(a, b)
+        torch.cuda.empty_cache()
+    aa.close()
+    ab.close()
