@@ -235,8 +235,9 @@ int lbm_training_pairs(lbm_ctx* coarse, const float* a_dev, const float* b_dev, 
                        float* x_dev, float* y_dev);
 
 /* Attach (or, with NULL, detach) a packed network to a D3Q27 x D3Q19 context
- * with Guo or velocity-shift forcing, FP32 storage and arithmetic and n % 64 == 0; later lbm_step calls run
- * the fused learned step.  packed_dev must stay valid while attached. */
+ * with Guo or velocity-shift forcing, FP32 storage and arithmetic, n % 64 == 0 and n <= 256
+ * (a coarse grid: 64^3 to 256^3); later lbm_step calls run the fused learned step.
+ * packed_dev must stay valid while attached.  Returns LBM_EINVAL otherwise. */
 int lbm_set_mlp(lbm_ctx* ctx, const void* packed_dev);
 
 /* ------------------------------------------------------------------------

@@ -30,6 +30,10 @@ CFLAGS = [
     # kernel then follows its source, so two kernels that share the collision
     # code (the plain and the learned step) round it identically
     "-ffp-contract=on",
+    # MFMA results in ordinary VGPRs rather than accumulation registers: the fused
+    # learned step reads every product back into VALU code, which AGPRs would turn
+    # into one v_accvgpr_read per result register
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
 ]
 
 

@@ -850,9 +850,9 @@ int lbm_set_mlp(lbm_ctx* c, const void* packed) {
   if (!c) { set_err(g_err, "ctx is NULL"); return LBM_EINVAL; }
   if (packed) {
     if (c->p.q_f != 27 || c->p.q_g != 19 || c->p.storage != LBM_FP32 || c->p.compute != LBM_COMPUTE_FP32 ||
-        c->p.n % 64 != 0 || !learned_forcing(c)) {
+        c->p.n % 64 != 0 || c->p.n > 256 || !learned_forcing(c)) {
       set_err(c->err, "the learned step needs D3Q27 x D3Q19, Guo or velocity-shift forcing, FP32 storage "
-                      "and arithmetic, n %% 64 == 0");
+                      "and arithmetic, n %% 64 == 0 and n <= 256");
       return LBM_EINVAL;
     }
     if ((uintptr_t)packed % 16) { set_err(c->err, "packed network must be 16-byte aligned"); return LBM_EINVAL; }

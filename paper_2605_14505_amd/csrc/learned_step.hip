@@ -13,7 +13,7 @@
 //   correction dF = M^-1 [0, dm], dm in two BF16 halves, whose result rows are the
 //              populations the lane owns.
 // No LDS, no block barriers except the diagnostic reduction.  Launched with 256-thread
-// blocks over n^3 / 128 blocks (n % 64 == 0).
+// blocks over n^3 / 128 blocks (n % 64 == 0, n <= 256).
 #include "lbm_kernels.hpp"
 #include "learned.hpp"
 #include "mlp_device.hpp"
@@ -57,6 +57,17 @@ __device__ __forceinline__ Dir dir_of(int p) {
   if (p >= 0 && p < 27) d = Dir{SF::ex[p], SF::ey[p], SF::ez[p], opp(p), (float)SF::w[p]};
   if (p >= 27) d = Dir{SG::ex[p - 27], SG::ey[p - 27], SG::ez[p - 27], 27 + opp(p - 27), (float)SG::w[p - 27]};
   return d;
+}
+
+// A lattice of up to 256^3 nodes (46 arrays, FP32) spans less than 4 GiB, so a
+// population is addressed as the lattice's base, uniform across the wavefront, plus
+// a 32-bit byte offset that folds in the lane's own array (the halves of a node own
+// different arrays).
+__device__ __forceinline__ const float* at_byte(const float* base, uint32_t bytes) {
+  return (const float*)((const char*)base + bytes);
+}
+__device__ __forceinline__ float* at_byte(float* base, uint32_t bytes) {
+  return (float*)((char*)base + bytes);
 }
 
 // array (population slot) and node offset of the load (GATHER) or store of population p
@@ -127,7 +138,7 @@ __global__ __launch_bounds__(256) void learned_step_kernel(float* __restrict__ p
     if ((h ? p1 : p0) >= 0) {
       const int arr = h ? a1 : a0;
       const uint32_t off = h ? o1 : o0;
-      v[s] = load_as<float>(at_node(src + (int64_t)arr * geo.stride, off));
+      v[s] = load_as<float>(at_byte(src, ((uint32_t)arr * (uint32_t)geo.stride + off) * 4u));
     }
   }
   // Direction of slot s in this half: sg * e0(s), e0 the half-0 direction; the
@@ -339,7 +350,7 @@ __global__ __launch_bounds__(256) void learned_step_kernel(float* __restrict__ p
     if ((h ? p1 : p0) >= 0) {
       const int arr = h ? a1 : a0;
       const uint32_t off = h ? o1 : o0;
-      store_as(at_node(dst + (int64_t)arr * geo.stride, off), v[s]);
+      store_as(at_byte(dst, ((uint32_t)arr * (uint32_t)geo.stride + off) * 4u), v[s]);
     }
   }
 
@@ -384,7 +395,7 @@ hipError_t by_mode(int mode, bool diag, int n, hipStream_t st, float* pop, float
 hipError_t launch_learned_step(int forcing, int mode, int flags, int n, hipStream_t st, float* pop,
                                float* dst, Geometry geo, PhysConsts c, float* fields, double* partials,
                                const void* packed) {
-  if (n % 64 != 0) return hipErrorInvalidValue;
+  if (n % 64 != 0 || n > 256) return hipErrorInvalidValue;     // 32-bit byte offsets
   const bool diag = (flags & K_PARTIALS) != 0;
   if (forcing == FORCE_GUO) return by_mode<FORCE_GUO>(mode, diag, n, st, pop, dst, geo, c, fields, partials, packed);
   if (forcing == FORCE_SHIFT) return by_mode<FORCE_SHIFT>(mode, diag, n, st, pop, dst, geo, c, fields, partials, packed);

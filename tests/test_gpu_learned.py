@@ -257,3 +257,16 @@ def test_learned_form_rejects_other_forcing_schemes(forcing):
     y = torch.empty((64 ** 3, 41), dtype=torch.float32, device=DEV)
     with pytest.raises(stgv.LbmError):
         stgv.lbm_training_pairs(sim.ctx, coarse, coarse, coarse, x, y)
+
+
+@pytest.mark.parametrize("n,storage", [(320, "fp32"), (96, "fp32"), (64, "fp16")])
+def test_learned_form_rejects_unsupported_boxes(n, storage):
+    # the fused learned step addresses a lattice of at most 256^3 nodes with 32-bit byte
+    # offsets, runs 128-node blocks (n % 64 == 0) and reads FP32 populations
+    sim = stgv.Simulation(**dict(_learned_kw(), n=n, storage=storage))
+    packed = packed_net(L.init_params(0), (np.zeros(47), np.ones(47), np.ones(41)))
+    with pytest.raises(stgv.LbmError) as ei:
+        sim.set_mlp(packed)
+    assert ei.value.status == stgv.LBM_EINVAL
+    assert "n <= 256" in str(ei.value)
+    sim.close()
