@@ -435,3 +435,41 @@ def test_large_512_staged_odd_step_equals_ab_push(storage):
         torch.cuda.empty_cache()
     aa.close()
     ab.close()
+
+
+def test_maximum_box_1024_fp16_sampled_parity():
+    # The largest box the library takes (n = 1024: 2^30 nodes, 98.8 GB of FP16 state, node
+    # offsets at the top of their 32-bit range).  The state is read raw at sampled nodes
+    # after two steps, when the AA layout is back in natural order (slot i at node x); the
+    # samples include the box corners and the x-edges of the 256-node blocks, where the
+    # staged odd step stores across block edges.
+    torch.cuda.empty_cache()
+    n, steps = 1024, 2
+    kw = dict(n=n, q_f=27, q_g=19, forcing="shift", storage="fp16", u0=0.05, re=3200.0, fr=0.5,
+              sc=0.7, g_over_n=0.02, noise_amp=1e-6, seed=0)
+    sim = gpu_sim(**kw)
+    sim.step(steps)
+    torch.cuda.synchronize()
+    q = 46
+    stride = sim.pop.numel() // (q * 2)
+    state = sim.pop.view(torch.float16)
+    nodes = sample_nodes(n, 12, seed=1) + [(5, 700, x) for x in (255, 256, 767, 768)]
+    lin = torch.tensor([x + n * (y + n * z) for z, y, x in nodes], dtype=torch.int64, device=state.device)
+    idx = (torch.arange(q, device=state.device, dtype=torch.int64)[:, None] * stride + lin[None, :])
+    got = state[idx].float().cpu().numpy().astype(np.float64)          # (q, samples)
+    sim.close()
+    del sim, state
+    torch.cuda.empty_cache()
+    p = oracle_params(kw)
+    U = model.units(p)
+    lf, lg = lat.BY_Q[p.q_f], lat.BY_Q[p.q_g]
+    worst = 0.0
+    for k, c in enumerate(nodes):
+        f, g = model.init_tgv_patch(p, c, steps)
+        for _ in range(steps):
+            fs, gs, _ = model.collide(f, g, lf, lg, U)
+            f, g = model.stream(fs, lf), model.stream(gs, lg)
+        ref = np.concatenate([f[:, steps, steps, steps] - lf.w, g[:, steps, steps, steps] - lg.w])
+        worst = max(worst, float(np.abs(got[:, k] - ref).max() / np.abs(ref).max()))
+    print(f"\nsampled {len(nodes)} nodes of {n}^3 FP16 after {steps} steps: worst rel err {worst:.3e}")
+    assert worst < (steps + 2) * 2.0 ** -11
