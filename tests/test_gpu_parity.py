@@ -473,3 +473,42 @@ def test_maximum_box_1024_fp16_sampled_parity():
         worst = max(worst, float(np.abs(got[:, k] - ref).max() / np.abs(ref).max()))
     print(f"\nsampled {len(nodes)} nodes of {n}^3 FP16 after {steps} steps: worst rel err {worst:.3e}")
     assert worst < (steps + 2) * 2.0 ** -11
+
+
+# ---------------------------------------------------------------------------
+# degenerate cases: no stratification, no steps
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("forcing", ["guo", "shift"])
+def test_unstratified_parity_and_zero_potential_energy(forcing):
+    # Fr = inf: G = 0, no buoyancy acts and the scalar is a passive tracer of the 1e-6
+    # noise, so rho' is tiny against the FP32 rounding of the velocity terms its lattice
+    # stores; the bar is that of the other parity cases, max(1e-5, 2.5 x the oracle's own
+    # error with FP32 storage).  E_p and eps_p are exactly zero.
+    kw = c1_kw(fr=math.inf, forcing=forcing)
+    ref = oracle_fields_series(tuple(sorted(kw.items())), (100,))
+    floor = storage_floor(kw, 100, "fp32")
+    sim = gpu_sim(compute="fp64", diag_every=50, **kw)
+    sim.step(100)
+    err = field_errors(sim.fields().cpu().numpy(), ref[100])
+    recs = sim.diagnostics()
+    sim.close()
+    print(f"\nunstratified {forcing}: {err}\n  fp32-storage floor {floor}")
+    for k in FIELDS:
+        assert err[k] <= max(1e-5, K_ARITH["fp64"] * floor[k]), (k, err[k], floor[k])
+    assert [r["step"] for r in recs] == [0, 50]
+    assert all(r["ep"] == 0.0 and r["eps_p"] == 0.0 for r in recs)
+    assert all(r["ek"] > 0.0 and r["eps_k"] > 0.0 for r in recs)
+
+
+@pytest.mark.parametrize("layout", ["aa", "ab"])
+def test_zero_steps_change_nothing(layout):
+    sim = gpu_sim(layout=layout, diag_every=1, **c1_kw(n=16))
+    before = sim.populations().clone()
+    sim.step(0)
+    assert stgv.lbm_get_step(sim.ctx) == 0
+    assert torch.equal(sim.populations(), before)
+    assert sim.diagnostics() == []
+    sim.step(1)                                   # the record of step 0 is queued with it
+    assert stgv.lbm_get_step(sim.ctx) == 1
+    assert [r["step"] for r in sim.diagnostics()] == [0]
+    sim.close()
