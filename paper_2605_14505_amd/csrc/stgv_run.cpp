@@ -3,14 +3,18 @@
 //   stgv_run [--n 128] [--qf 27] [--qg 19] [--forcing shift|guo|edm|hcz]
 //            [--storage fp32|fp16|bf16] [--compute fp32|fp64] [--layout aa|ab]
 //            [--re 1600] [--fr 1] [--sc 0.7] [--u0 0.05] [--gn 0.02] [--noise 1e-6]
-//            [--seed 0] [--steps 1000] [--diag 50]
+//            [--seed 0] [--steps 1000] [--diag 50] [--spectrum FILE]
 //
 // Allocates the population and work buffers with hipMalloc, queues the initial state
 // and the steps, drains the diagnostic records (printed as CSV: step, t, E_k, E_p,
-// eps_k, eps_p, mass, max|u|) and reports the run's MLUPS from HIP events.  Exit status:
-// 0 on success, 2 for bad arguments, 1 for a library or HIP error.
+// eps_k, eps_p, mass, max|u|) and reports the run's MLUPS from HIP events.  With two
+// or more records it also prints the post-processing of Section 4 over the whole run
+// (bulk flux coefficient, turbulent Froude number, peak buoyancy Reynolds number);
+// --spectrum writes the kinetic-energy spectrum of the final state (k, E(k) per line).
+// Exit status: 0 on success, 2 for bad arguments, 1 for a library or HIP error.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -27,7 +31,7 @@ void usage() {
                "usage: stgv_run [--n N] [--qf Q] [--qg Q] [--forcing shift|guo|edm|hcz]\n"
                "                [--storage fp32|fp16|bf16] [--compute fp32|fp64] [--layout aa|ab]\n"
                "                [--re RE] [--fr FR] [--sc SC] [--u0 U0] [--gn G/N] [--noise A]\n"
-               "                [--seed S] [--steps K] [--diag D]\n");
+               "                [--seed S] [--steps K] [--diag D] [--spectrum FILE]\n");
 }
 
 bool pick(const char* v, const char* const* names, int count, int32_t* out) {
@@ -41,6 +45,40 @@ int fail(const char* what, int status, const lbm_ctx* ctx) {
   return 1;
 }
 
+// The kinetic-energy spectrum of the current state into `path` (k, E(k) per line).
+int write_spectrum(lbm_ctx* ctx, int n, const char* path) {
+  const int32_t shells = lbm_spectrum_shells(n);
+  size_t work_bytes = 0;
+  int st = lbm_spectrum_work_bytes(n, &work_bytes);
+  if (st != LBM_OK) return fail("spectrum work size", st, nullptr);
+  void *work = nullptr, *dev = nullptr;
+  if (hipMalloc(&work, work_bytes) != hipSuccess || hipMalloc(&dev, (size_t)shells * sizeof(double)) != hipSuccess) {
+    std::fprintf(stderr, "stgv_run: hipMalloc for the spectrum failed\n");
+    return 1;
+  }
+  int rc = 0;
+  std::vector<double> e((size_t)shells);
+  st = lbm_ke_spectrum(ctx, work, work_bytes, static_cast<double*>(dev));
+  if (st != LBM_OK) {
+    rc = fail("spectrum", st, ctx);
+  } else if (hipMemcpy(e.data(), dev, e.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+    std::fprintf(stderr, "stgv_run: copying the spectrum failed\n");
+    rc = 1;
+  } else {
+    FILE* f = std::fopen(path, "w");
+    if (!f) {
+      std::fprintf(stderr, "stgv_run: cannot write %s\n", path);
+      rc = 1;
+    } else {
+      for (int32_t k = 0; k < shells; ++k) std::fprintf(f, "%d %.12e\n", k, e[(size_t)k]);
+      std::fclose(f);
+    }
+  }
+  (void)hipFree(work);
+  (void)hipFree(dev);
+  return rc;
+}
+
 }  // namespace
 
 int main(int argc, char** argv) {
@@ -49,6 +87,7 @@ int main(int argc, char** argv) {
   p.compute = LBM_COMPUTE_FP32; p.layout = LBM_LAYOUT_AA; p.diag_every = 50; p.pad = -1;
   p.u0 = 0.05; p.re = 1600.0; p.fr = 1.0; p.sc = 0.7; p.g_over_n = 0.02; p.noise_amp = 1e-6; p.seed = 0;
   long long steps = 1000;
+  const char* spectrum_path = nullptr;
   static const char* const forcings[] = {"guo", "shift", "edm", "hcz"};
   static const char* const storages[] = {"fp32", "fp16", "bf16"};
   static const char* const computes[] = {"fp32", "fp64"};
@@ -75,6 +114,7 @@ int main(int argc, char** argv) {
     else if (a == "--seed") p.seed = std::strtoull(v, nullptr, 10);
     else if (a == "--steps") steps = std::atoll(v);
     else if (a == "--diag") p.diag_every = std::atoi(v);
+    else if (a == "--spectrum") spectrum_path = v;
     else ok = false;
     if (!ok) { std::fprintf(stderr, "stgv_run: bad option %s %s\n", a.c_str(), v); usage(); return 2; }
   }
@@ -95,7 +135,7 @@ int main(int argc, char** argv) {
   if (st != LBM_OK) return fail("initial state", st, nullptr);
 
   std::printf("step,t,ek,ep,eps_k,eps_p,mass,umax\n");
-  std::vector<lbm_diag> recs(4096);
+  std::vector<lbm_diag> recs(4096), all;
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
@@ -110,9 +150,11 @@ int main(int argc, char** argv) {
     done += k;
     int32_t got = 0;
     st = lbm_diagnostics(ctx, recs.data(), (int32_t)recs.size(), &got);
-    for (int32_t r = 0; r < got; ++r)
+    for (int32_t r = 0; r < got; ++r) {
       std::printf("%lld,%.6f,%.10e,%.10e,%.10e,%.10e,%.10e,%.6e\n", (long long)recs[r].step, recs[r].t,
                   recs[r].ek, recs[r].ep, recs[r].eps_k, recs[r].eps_p, recs[r].mass, recs[r].umax);
+      all.push_back(recs[r]);
+    }
     if (st != LBM_OK) rc = fail("diagnostics", st, ctx);
   }
   (void)hipEventRecord(e1, stream);
@@ -122,6 +164,15 @@ int main(int argc, char** argv) {
   const double n3 = (double)p.n * p.n * p.n;
   std::fprintf(stderr, "stgv_run: %lld steps of %d^3 D3Q%dxD3Q%d in %.1f ms: %.1f MLUPS\n", steps, p.n, p.q_f,
                p.q_g, ms, steps > 0 && ms > 0.f ? n3 * steps / (ms * 1e-3) / 1e6 : 0.0);
+  if (rc == 0 && all.size() >= 2) {
+    lbm_post post{};
+    st = lbm_postprocess(all.data(), (int32_t)all.size(), p.re, p.fr, all.back().t, nullptr, nullptr, &post);
+    if (st != LBM_OK) rc = fail("post-processing", st, nullptr);
+    else
+      std::fprintf(stderr, "stgv_run: t <= %.4f (%d records): Gamma_b %.10e  Fr_t %.10e  R_max %.10e at t = %.4f\n",
+                   all.back().t, post.used, post.gamma_b, post.fr_t, post.r_max, post.t_r_max);
+  }
+  if (rc == 0 && spectrum_path) rc = write_spectrum(ctx, p.n, spectrum_path);
   lbm_destroy(ctx);
   (void)hipStreamDestroy(stream);
   (void)hipFree(pop);

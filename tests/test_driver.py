@@ -40,7 +40,7 @@ def test_parameter_errors_stop_before_the_gpu(args, msg):
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("forcing,storage", [("shift", "fp32"), ("guo", "fp16")])
-def test_driver_records_match_the_binding(forcing, storage):
+def test_driver_records_match_the_binding(forcing, storage, tmp_path):
     import torch
 
     from paper_2605_14505_amd import stgv
@@ -49,7 +49,7 @@ def test_driver_records_match_the_binding(forcing, storage):
               g_over_n=0.02, noise_amp=1e-6, seed=5, diag_every=25)
     r = run("--n", 32, "--qf", 27, "--qg", 19, "--forcing", forcing, "--storage", storage, "--re", 400, "--fr", 1,
             "--sc", 0.7, "--u0", 0.05, "--gn", 0.02, "--noise", 1e-6, "--seed", 5, "--steps", 200, "--diag", 25,
-            timeout=120)
+            "--spectrum", tmp_path / "spectrum.txt", timeout=120)
     assert r.returncode == 0, r.stderr
     assert "MLUPS" in r.stderr
     lines = r.stdout.strip().splitlines()
@@ -58,6 +58,7 @@ def test_driver_records_match_the_binding(forcing, storage):
     sim = stgv.Simulation(device="cuda:0", **kw)
     sim.step(200)
     recs = sim.diagnostics()
+    spec = sim.spectrum().cpu().numpy()
     sim.close()
     torch.cuda.synchronize()
     assert len(rows) == len(recs) == 8
@@ -66,3 +67,18 @@ def test_driver_records_match_the_binding(forcing, storage):
         # same library, same kernels: equal up to the 11 significant digits printed
         for j, key in enumerate(("ek", "ep", "eps_k", "eps_p", "mass"), start=2):
             assert row[j] == pytest.approx(rec[key], rel=1e-10, abs=1e-300), (rec["step"], key)
+    # the post-processing line: the binding's lbm_postprocess over the same records
+    _, _, post = stgv.lbm_postprocess(recs, re=400.0, fr=1.0, t_end=recs[-1]["t"])
+    line = [ln for ln in r.stderr.splitlines() if "Gamma_b" in ln][0].split()
+    got = {k: float(line[line.index(k) + 1]) for k in ("Gamma_b", "Fr_t", "R_max")}
+    assert got["Gamma_b"] == pytest.approx(post["gamma_b"], rel=1e-5)
+    assert got["Fr_t"] == pytest.approx(post["fr_t"], rel=1e-5)
+    assert got["R_max"] == pytest.approx(post["r_max"], rel=1e-5)
+    # the spectrum file: the binding's spectrum of the same final state
+    table = [ln.split() for ln in (tmp_path / "spectrum.txt").read_text().splitlines()]
+    assert [int(t[0]) for t in table] == list(range(stgv.lbm_spectrum_shells(32)))
+    # the transforms are single precision and the two processes' results differ in the
+    # last bits (measured ~2e-9 of a shell), so the bar is relative to the total energy
+    total = float(spec.sum())
+    for (k, e), ref in zip(table, spec):
+        assert abs(float(e) - ref) <= 1e-7 * total, k
