@@ -106,8 +106,11 @@ def main():
                 fb, wb = fetch[k] * f_scale * 1024, write[k] * w_scale * 1024
                 fh.write(f"# {k[:110]}\n#   fetch {fb / 1e9:.4f} GB  write {wb / 1e9:.4f} GB  "
                          f"total/algorithmic {(fb + wb) / algo:.4f}\n")
-                m = re.search(r"lbm_step_kernel<[^>]*, (\d+)>\(", k)
-                if m and m.group(1) == "1":          # plain steps (no diagnostic outputs)
+                # plain steps (no diagnostic outputs): FLAGS == 1, the last template
+                # argument, in the demangled or the mangled name
+                m = re.search(r"lbm_step_kernel<[^>]*, (\d+)>\(", k) or \
+                    re.search(r"lbm_step_kernelI.*ELi(\d+)EEEv", k)
+                if m and m.group(1) == "1":
                     plain.append(fb + wb)
             per_launch = sum(plain) / len(plain) if plain else float("nan")
             fh.write(f"source_hash = {kernel_source_hash()}\n")
