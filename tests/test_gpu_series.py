@@ -45,3 +45,15 @@ def test_energy_and_dissipation_histories_match_the_oracle(compute):
     for k in KEYS:
         # relative to each history's largest value; the storage floor is ~1e-9 - 1e-8 here
         assert err[k] <= max(1e-6, 100.0 * floor[k]), (k, err[k], floor[k])
+
+
+@pytest.mark.parametrize("storage,bar", [("fp16", 2 * 2.0 ** -11), ("bf16", 8 * 2.0 ** -8)])
+def test_reduced_storage_histories_against_the_oracle(storage, bar):
+    # The precision forms' energy and dissipation histories against the FP64 oracle over the
+    # same 2500 steps.  Deviations stored in FP16 (unit roundoff u = 2^-11) or BF16
+    # (u = 2^-8) with FP32 arithmetic; measured 0.4 - 0.8 u (FP16) and 3 - 5 u (BF16): BF16's
+    # rounding of the velocity-carrying deviations biases the decay as well as adding noise.
+    err = _errors(_gpu_history(storage=storage), GOLD["fp64"])
+    print(f"\n{storage} storage, {GOLD['steps']} steps at 64^3: errors against the FP64 oracle {err}")
+    for k in KEYS:
+        assert err[k] <= bar, (k, err[k], bar)
