@@ -4,6 +4,7 @@
 //            [--storage fp32|fp16|bf16] [--compute fp32|fp64] [--layout aa|ab]
 //            [--re 1600] [--fr 1] [--sc 0.7] [--u0 0.05] [--gn 0.02] [--noise 1e-6]
 //            [--seed 0] [--steps 1000] [--diag 50] [--spectrum FILE]
+//            [--checkpoint FILE] [--resume FILE]
 //
 // Allocates the population and work buffers with hipMalloc, queues the initial state
 // and the steps, drains the diagnostic records (printed as CSV: step, t, E_k, E_p,
@@ -11,7 +12,11 @@
 // or more records it also prints the post-processing of Section 4 over the whole run
 // (bulk flux coefficient, turbulent Froude number, peak buoyancy Reynolds number);
 // --spectrum writes the kinetic-energy spectrum of the final state (k, E(k) per line).
-// Exit status: 0 on success, 2 for bad arguments, 1 for a library or HIP error.
+// --checkpoint writes the final state (header + the FP32 populations of
+// lbm_read_populations) and --resume continues from such a file for --steps more
+// steps; a resumed run reproduces the uninterrupted one bit for bit.
+// Exit status: 0 on success, 2 for bad arguments (a resume file that is not a
+// checkpoint of the run's box included), 1 for a library or HIP error.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,7 +36,8 @@ void usage() {
                "usage: stgv_run [--n N] [--qf Q] [--qg Q] [--forcing shift|guo|edm|hcz]\n"
                "                [--storage fp32|fp16|bf16] [--compute fp32|fp64] [--layout aa|ab]\n"
                "                [--re RE] [--fr FR] [--sc SC] [--u0 U0] [--gn G/N] [--noise A]\n"
-               "                [--seed S] [--steps K] [--diag D] [--spectrum FILE]\n");
+               "                [--seed S] [--steps K] [--diag D] [--spectrum FILE]\n"
+               "                [--checkpoint FILE] [--resume FILE]\n");
 }
 
 bool pick(const char* v, const char* const* names, int count, int32_t* out) {
@@ -79,6 +85,84 @@ int write_spectrum(lbm_ctx* ctx, int n, const char* path) {
   return rc;
 }
 
+// Checkpoint file: this header, then (q_f + q_g) n^3 FP32 population deviations in the
+// order of lbm_read_populations.
+struct CkptHeader {
+  char magic[8];       // "STGVCKP1"
+  int32_t n, q_f, q_g, storage;
+  int64_t step;
+};
+constexpr char kMagic[8] = {'S', 'T', 'G', 'V', 'C', 'K', 'P', '1'};
+
+int save_state(lbm_ctx* ctx, const lbm_params& p, const char* path) {
+  const size_t count = (size_t)(p.q_f + p.q_g) * p.n * p.n * p.n;
+  void* dev = nullptr;
+  if (hipMalloc(&dev, count * sizeof(float)) != hipSuccess) {
+    std::fprintf(stderr, "stgv_run: hipMalloc for the checkpoint failed\n");
+    return 1;
+  }
+  std::vector<float> host(count);
+  int rc = 0;
+  const int st = lbm_read_populations(ctx, static_cast<float*>(dev));
+  if (st != LBM_OK) {
+    rc = fail("reading the populations", st, ctx);
+  } else if (hipMemcpy(host.data(), dev, count * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess) {
+    std::fprintf(stderr, "stgv_run: copying the populations failed\n");
+    rc = 1;
+  } else {
+    CkptHeader hd{};
+    std::memcpy(hd.magic, kMagic, sizeof(kMagic));
+    hd.n = p.n; hd.q_f = p.q_f; hd.q_g = p.q_g; hd.storage = p.storage;
+    hd.step = lbm_get_step(ctx);
+    FILE* f = std::fopen(path, "wb");
+    if (!f || std::fwrite(&hd, sizeof(hd), 1, f) != 1 || std::fwrite(host.data(), sizeof(float), count, f) != count) {
+      std::fprintf(stderr, "stgv_run: cannot write %s\n", path);
+      rc = 1;
+    }
+    if (f) std::fclose(f);
+  }
+  (void)hipFree(dev);
+  return rc;
+}
+
+// Read a checkpoint of this run's box and stencils into host memory (before any GPU
+// work, so that a wrong file is an argument error); returns 0 or prints why not.
+int read_checkpoint(const lbm_params& p, const char* path, std::vector<float>& host, int64_t& step) {
+  FILE* f = std::fopen(path, "rb");
+  if (!f) { std::fprintf(stderr, "stgv_run: cannot read %s\n", path); return 2; }
+  CkptHeader hd{};
+  const size_t count = (size_t)(p.q_f + p.q_g) * p.n * p.n * p.n;
+  host.resize(count);
+  const bool ok = std::fread(&hd, sizeof(hd), 1, f) == 1 && std::memcmp(hd.magic, kMagic, sizeof(kMagic)) == 0 &&
+                  hd.n == p.n && hd.q_f == p.q_f && hd.q_g == p.q_g && hd.step >= 0 &&
+                  std::fread(host.data(), sizeof(float), count, f) == count;
+  std::fclose(f);
+  if (!ok) {
+    std::fprintf(stderr, "stgv_run: %s is not a checkpoint of a %d^3 D3Q%dxD3Q%d run\n", path, p.n, p.q_f, p.q_g);
+    return 2;
+  }
+  step = hd.step;
+  return 0;
+}
+
+int load_state(lbm_ctx* ctx, const std::vector<float>& host, int64_t step) {
+  void* dev = nullptr;
+  if (hipMalloc(&dev, host.size() * sizeof(float)) != hipSuccess) {
+    std::fprintf(stderr, "stgv_run: hipMalloc for the checkpoint failed\n");
+    return 1;
+  }
+  int rc = 0;
+  if (hipMemcpy(dev, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+    std::fprintf(stderr, "stgv_run: copying the populations failed\n");
+    rc = 1;
+  } else {
+    const int st = lbm_load_populations(ctx, static_cast<const float*>(dev), step);
+    if (st != LBM_OK) rc = fail("loading the populations", st, ctx);
+  }
+  (void)hipFree(dev);
+  return rc;
+}
+
 }  // namespace
 
 int main(int argc, char** argv) {
@@ -88,6 +172,8 @@ int main(int argc, char** argv) {
   p.u0 = 0.05; p.re = 1600.0; p.fr = 1.0; p.sc = 0.7; p.g_over_n = 0.02; p.noise_amp = 1e-6; p.seed = 0;
   long long steps = 1000;
   const char* spectrum_path = nullptr;
+  const char* checkpoint_path = nullptr;
+  const char* resume_path = nullptr;
   static const char* const forcings[] = {"guo", "shift", "edm", "hcz"};
   static const char* const storages[] = {"fp32", "fp16", "bf16"};
   static const char* const computes[] = {"fp32", "fp64"};
@@ -115,6 +201,8 @@ int main(int argc, char** argv) {
     else if (a == "--steps") steps = std::atoll(v);
     else if (a == "--diag") p.diag_every = std::atoi(v);
     else if (a == "--spectrum") spectrum_path = v;
+    else if (a == "--checkpoint") checkpoint_path = v;
+    else if (a == "--resume") resume_path = v;
     else ok = false;
     if (!ok) { std::fprintf(stderr, "stgv_run: bad option %s %s\n", a.c_str(), v); usage(); return 2; }
   }
@@ -123,6 +211,12 @@ int main(int argc, char** argv) {
   size_t pop_bytes = 0, work_bytes = 0;
   int st = lbm_query_sizes(&p, &pop_bytes, &work_bytes);     // validates every parameter on the CPU
   if (st != LBM_OK) return fail("parameters", st, nullptr);
+  std::vector<float> resume_state;
+  int64_t resume_step = 0;
+  if (resume_path) {
+    const int r = read_checkpoint(p, resume_path, resume_state, resume_step);
+    if (r != 0) return r;
+  }
   void *pop = nullptr, *work = nullptr;
   if (hipMalloc(&pop, pop_bytes) != hipSuccess || hipMalloc(&work, work_bytes) != hipSuccess) {
     std::fprintf(stderr, "stgv_run: hipMalloc of %zu + %zu bytes failed\n", pop_bytes, work_bytes);
@@ -133,6 +227,11 @@ int main(int argc, char** argv) {
   lbm_ctx* ctx = nullptr;
   st = lbm_init_tgv(&p, pop, pop_bytes, work, work_bytes, stream, &ctx);
   if (st != LBM_OK) return fail("initial state", st, nullptr);
+  if (resume_path) {
+    const int r = load_state(ctx, resume_state, resume_step);
+    if (r != 0) { lbm_destroy(ctx); return r; }
+    std::vector<float>().swap(resume_state);
+  }
 
   std::printf("step,t,ek,ep,eps_k,eps_p,mass,umax\n");
   std::vector<lbm_diag> recs(4096), all;
@@ -173,6 +272,7 @@ int main(int argc, char** argv) {
                    all.back().t, post.used, post.gamma_b, post.fr_t, post.r_max, post.t_r_max);
   }
   if (rc == 0 && spectrum_path) rc = write_spectrum(ctx, p.n, spectrum_path);
+  if (rc == 0 && checkpoint_path) rc = save_state(ctx, p, checkpoint_path);
   lbm_destroy(ctx);
   (void)hipStreamDestroy(stream);
   (void)hipFree(pop);

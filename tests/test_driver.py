@@ -82,3 +82,44 @@ def test_driver_records_match_the_binding(forcing, storage, tmp_path):
     total = float(spec.sum())
     for (k, e), ref in zip(table, spec):
         assert abs(float(e) - ref) <= 1e-7 * total, k
+
+
+def _header(n, q_f=27, q_g=19, storage=0, step=0):
+    import struct
+    return b"STGVCKP1" + struct.pack("<iiiiq", n, q_f, q_g, storage, step)
+
+
+@pytest.mark.parametrize("content", [None, b"junk", "wrong_n", "truncated"])
+def test_resume_rejects_what_is_not_a_checkpoint_of_the_run(content, tmp_path):
+    # the file is read and checked before any GPU work: exit status 2
+    path = tmp_path / "state.bin"
+    if content == "wrong_n":
+        path.write_bytes(_header(16) + bytes(46 * 16 ** 3 * 4))
+    elif content == "truncated":
+        path.write_bytes(_header(32) + bytes(100))
+    elif content is not None:
+        path.write_bytes(content)
+    r = run("--n", 32, "--resume", path)
+    assert r.returncode == 2
+    assert str(path) in r.stderr
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+def test_checkpoint_and_resume_reproduce_the_uninterrupted_run(storage, tmp_path):
+    common = ["--n", 32, "--storage", storage, "--fr", 0.5, "--re", 400, "--diag", 25, "--seed", 3]
+    whole = run(*common, "--steps", 120, "--checkpoint", tmp_path / "whole.bin", timeout=120)
+    assert whole.returncode == 0, whole.stderr
+    # stop after an odd number of steps, so the run resumes in the other AA parity
+    first = run(*common, "--steps", 71, "--checkpoint", tmp_path / "part.bin", timeout=120)
+    assert first.returncode == 0, first.stderr
+    rest = run(*common, "--steps", 49, "--resume", tmp_path / "part.bin", "--checkpoint", tmp_path / "end.bin",
+               timeout=120)
+    assert rest.returncode == 0, rest.stderr
+    rows = {ln.split(",")[0]: ln for ln in whole.stdout.strip().splitlines()[1:]}
+    resumed = rest.stdout.strip().splitlines()[1:]
+    assert [ln.split(",")[0] for ln in resumed] == ["75", "100"]
+    for ln in resumed:
+        assert ln == rows[ln.split(",")[0]]
+    # the final states, header (step 120) included, are the same bytes
+    assert (tmp_path / "end.bin").read_bytes() == (tmp_path / "whole.bin").read_bytes()
