@@ -4,7 +4,7 @@
 //            [--storage fp32|fp16|bf16] [--compute fp32|fp64] [--layout aa|ab]
 //            [--re 1600] [--fr 1] [--sc 0.7] [--u0 0.05] [--gn 0.02] [--noise 1e-6]
 //            [--seed 0] [--steps 1000] [--diag 50] [--spectrum FILE]
-//            [--checkpoint FILE] [--resume FILE]
+//            [--checkpoint FILE] [--resume FILE] [--mlp FILE]
 //
 // Allocates the population and work buffers with hipMalloc, queues the initial state
 // and the steps, drains the diagnostic records (printed as CSV: step, t, E_k, E_p,
@@ -14,7 +14,9 @@
 // --spectrum writes the kinetic-energy spectrum of the final state (k, E(k) per line).
 // --checkpoint writes the final state (header + the FP32 populations of
 // lbm_read_populations) and --resume continues from such a file for --steps more
-// steps; a resumed run reproduces the uninterrupted one bit for bit.
+// steps; a resumed run reproduces the uninterrupted one bit for bit.  --mlp attaches a
+// trained network (the raw file `python -m paper_2605_14505_amd.learned --export`
+// writes), so the steps are the fused learned step.
 // Exit status: 0 on success, 2 for bad arguments (a resume file that is not a
 // checkpoint of the run's box included), 1 for a library or HIP error.
 #include <hip/hip_runtime.h>
@@ -37,7 +39,7 @@ void usage() {
                "                [--storage fp32|fp16|bf16] [--compute fp32|fp64] [--layout aa|ab]\n"
                "                [--re RE] [--fr FR] [--sc SC] [--u0 U0] [--gn G/N] [--noise A]\n"
                "                [--seed S] [--steps K] [--diag D] [--spectrum FILE]\n"
-               "                [--checkpoint FILE] [--resume FILE]\n");
+               "                [--checkpoint FILE] [--resume FILE] [--mlp FILE]\n");
 }
 
 bool pick(const char* v, const char* const* names, int count, int32_t* out) {
@@ -163,6 +165,51 @@ int load_state(lbm_ctx* ctx, const std::vector<float>& host, int64_t step) {
   return rc;
 }
 
+// A network file: "STGVMLP1", int32 parameter and normalisation counts, then the FP32
+// master parameters and normalisation in the layout lbm_mlp_pack reads.
+int read_network(const char* path, std::vector<float>& params, std::vector<float>& norm) {
+  FILE* f = std::fopen(path, "rb");
+  if (!f) { std::fprintf(stderr, "stgv_run: cannot read %s\n", path); return 2; }
+  char magic[8] = {0};
+  int32_t counts[2] = {0, 0};
+  params.resize(LBM_MLP_PARAMS);
+  norm.resize(LBM_MLP_NORM);
+  const bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "STGVMLP1", 8) == 0 &&
+                  std::fread(counts, sizeof(int32_t), 2, f) == 2 && counts[0] == LBM_MLP_PARAMS &&
+                  counts[1] == LBM_MLP_NORM &&
+                  std::fread(params.data(), sizeof(float), params.size(), f) == params.size() &&
+                  std::fread(norm.data(), sizeof(float), norm.size(), f) == norm.size();
+  std::fclose(f);
+  if (!ok) { std::fprintf(stderr, "stgv_run: %s is not a network file\n", path); return 2; }
+  return 0;
+}
+
+// Pack the network on the device and attach it; *packed stays allocated while attached.
+int attach_network(lbm_ctx* ctx, hipStream_t stream, const std::vector<float>& params,
+                   const std::vector<float>& norm, void** packed) {
+  void *dp = nullptr, *dn = nullptr;
+  if (hipMalloc(&dp, params.size() * sizeof(float)) != hipSuccess ||
+      hipMalloc(&dn, norm.size() * sizeof(float)) != hipSuccess ||
+      hipMalloc(packed, lbm_mlp_packed_bytes()) != hipSuccess) {
+    std::fprintf(stderr, "stgv_run: hipMalloc for the network failed\n");
+    return 1;
+  }
+  int rc = 0;
+  if (hipMemcpy(dp, params.data(), params.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(dn, norm.data(), norm.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+    std::fprintf(stderr, "stgv_run: copying the network failed\n");
+    rc = 1;
+  } else {
+    int st = lbm_mlp_pack(static_cast<const float*>(dp), static_cast<const float*>(dn), *packed, stream);
+    if (st == LBM_OK && hipStreamSynchronize(stream) != hipSuccess) st = LBM_EHIP;
+    if (st != LBM_OK) rc = fail("packing the network", st, nullptr);
+    else if ((st = lbm_set_mlp(ctx, *packed)) != LBM_OK) rc = fail("attaching the network", st, ctx);
+  }
+  (void)hipFree(dp);
+  (void)hipFree(dn);
+  return rc;
+}
+
 }  // namespace
 
 int main(int argc, char** argv) {
@@ -174,6 +221,7 @@ int main(int argc, char** argv) {
   const char* spectrum_path = nullptr;
   const char* checkpoint_path = nullptr;
   const char* resume_path = nullptr;
+  const char* mlp_path = nullptr;
   static const char* const forcings[] = {"guo", "shift", "edm", "hcz"};
   static const char* const storages[] = {"fp32", "fp16", "bf16"};
   static const char* const computes[] = {"fp32", "fp64"};
@@ -203,6 +251,7 @@ int main(int argc, char** argv) {
     else if (a == "--spectrum") spectrum_path = v;
     else if (a == "--checkpoint") checkpoint_path = v;
     else if (a == "--resume") resume_path = v;
+    else if (a == "--mlp") mlp_path = v;
     else ok = false;
     if (!ok) { std::fprintf(stderr, "stgv_run: bad option %s %s\n", a.c_str(), v); usage(); return 2; }
   }
@@ -215,6 +264,11 @@ int main(int argc, char** argv) {
   int64_t resume_step = 0;
   if (resume_path) {
     const int r = read_checkpoint(p, resume_path, resume_state, resume_step);
+    if (r != 0) return r;
+  }
+  std::vector<float> mlp_params, mlp_norm;
+  if (mlp_path) {
+    const int r = read_network(mlp_path, mlp_params, mlp_norm);
     if (r != 0) return r;
   }
   void *pop = nullptr, *work = nullptr;
@@ -231,6 +285,11 @@ int main(int argc, char** argv) {
     const int r = load_state(ctx, resume_state, resume_step);
     if (r != 0) { lbm_destroy(ctx); return r; }
     std::vector<float>().swap(resume_state);
+  }
+  void* packed = nullptr;
+  if (mlp_path) {
+    const int r = attach_network(ctx, stream, mlp_params, mlp_norm, &packed);
+    if (r != 0) { lbm_destroy(ctx); return r; }
   }
 
   std::printf("step,t,ek,ep,eps_k,eps_p,mass,umax\n");
@@ -274,6 +333,7 @@ int main(int argc, char** argv) {
   if (rc == 0 && spectrum_path) rc = write_spectrum(ctx, p.n, spectrum_path);
   if (rc == 0 && checkpoint_path) rc = save_state(ctx, p, checkpoint_path);
   lbm_destroy(ctx);
+  if (packed) (void)hipFree(packed);
   (void)hipStreamDestroy(stream);
   (void)hipFree(pop);
   (void)hipFree(work);

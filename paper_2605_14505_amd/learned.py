@@ -19,6 +19,7 @@ from __future__ import annotations
 import argparse
 import json
 import math
+import os
 import time
 
 import numpy as np
@@ -340,6 +341,26 @@ def with_gain(net, gain):
 
 GAINS = (0.0, 0.05, 0.1, 0.2, 0.35, 0.5, 1.0)
 
+# Raw network file read by the command-line driver (stgv_run --mlp): an 8-byte magic,
+# the parameter and normalisation counts (int32), then the FP32 parameters and the FP32
+# normalisation (x mean, x inverse scale, y scale x gain), little-endian.
+NET_MAGIC = b"STGVMLP1"
+
+
+def export_network(theta, norm, path, gain=1.0):
+    """Write the network (master parameters `theta`, normalisation `norm`) with its
+    correction scaled by `gain` in the driver's raw format."""
+    theta = np.asarray(theta, dtype=np.float32).ravel()
+    norm = np.asarray(norm, dtype=np.float64).ravel().copy()
+    if theta.size != NPARAM or norm.size != IN + IN + OUT:
+        raise ValueError(f"expected {NPARAM} parameters and {IN + IN + OUT} normalisation values")
+    norm[IN + IN:] *= gain
+    with open(path, "wb") as fh:
+        fh.write(NET_MAGIC)
+        fh.write(np.array([theta.size, norm.size], dtype="<i4").tobytes())
+        fh.write(theta.astype("<f4").tobytes())
+        fh.write(norm.astype("<f4").tobytes())
+
 
 def pipeline(nc=64, train_fr=(0.3, 1.0, 3.0), seeds=(0,), test_fr=0.6, t_end=30.0, snapshots=64,
              train_steps=6000, batch=16384, lr=2e-3, gains=GAINS, diag_records=100, device="cuda:0",
@@ -431,7 +452,19 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--out", default=None, help="JSON summary path")
     ap.add_argument("--save", default=None, help="npz path for the trained network")
+    ap.add_argument("--export", default=None,
+                    help="only write the network of --net (default: the shipped one) in the raw "
+                         "format of stgv_run --mlp, at --gain (default: its validated gain)")
+    ap.add_argument("--net", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "data",
+                                                  "learned64.npz"))
+    ap.add_argument("--gain", type=float, default=None)
     a = ap.parse_args(argv)
+    if a.export:
+        z = np.load(a.net, allow_pickle=False)
+        gain = float(z["gain"]) if a.gain is None else a.gain
+        export_network(z["theta"], z["norm"], a.export, gain)
+        print(f"wrote {a.export} (gain {gain})")
+        return
     summary, _, _ = pipeline(a.nc, tuple(a.train_fr), tuple(a.seeds), a.test_fr, a.t_end, a.snapshots,
                              a.train_steps, a.batch, a.lr, log=lambda s: print(s, flush=True), save=a.save)
     text = json.dumps(summary, indent=1)

@@ -123,3 +123,62 @@ def test_checkpoint_and_resume_reproduce_the_uninterrupted_run(storage, tmp_path
         assert ln == rows[ln.split(",")[0]]
     # the final states, header (step 120) included, are the same bytes
     assert (tmp_path / "end.bin").read_bytes() == (tmp_path / "whole.bin").read_bytes()
+
+
+def test_network_export_round_trip_and_rejection(tmp_path):
+    import numpy as np
+
+    from paper_2605_14505_amd import learned
+
+    rng = np.random.default_rng(0)
+    theta = rng.standard_normal(learned.NPARAM).astype(np.float32)
+    norm = np.concatenate([rng.standard_normal(47), rng.random(47), rng.random(41) + 0.5])
+    path = tmp_path / "net.bin"
+    learned.export_network(theta, norm, path, gain=0.25)
+    raw = path.read_bytes()
+    assert raw[:8] == learned.NET_MAGIC
+    counts = np.frombuffer(raw[8:16], dtype="<i4")
+    assert list(counts) == [learned.NPARAM, 135]
+    body = np.frombuffer(raw[16:], dtype="<f4")
+    np.testing.assert_array_equal(body[:learned.NPARAM], theta)
+    np.testing.assert_array_equal(body[learned.NPARAM:learned.NPARAM + 94], norm[:94].astype(np.float32))
+    np.testing.assert_array_equal(body[learned.NPARAM + 94:], (norm[94:] * 0.25).astype(np.float32))
+    # the driver checks a network file before any GPU work
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(raw[:100])
+    r = run("--n", 64, "--mlp", bad)
+    assert r.returncode == 2 and "not a network file" in r.stderr
+
+
+@pytest.mark.gpu
+def test_driver_runs_the_learned_step_like_the_binding(tmp_path):
+    import numpy as np
+    import torch
+
+    from paper_2605_14505_amd import learned, stgv
+
+    z = np.load(os.path.join(ROOT, "paper_2605_14505_amd", "data", "learned64.npz"), allow_pickle=False)
+    learned.export_network(z["theta"], z["norm"], tmp_path / "net.bin", gain=1.0)
+    r = run("--n", 64, "--fr", 0.6, "--re", 1600, "--sc", 0.7, "--steps", 100, "--diag", 25, "--mlp",
+            tmp_path / "net.bin", timeout=120)
+    assert r.returncode == 0, r.stderr
+    rows = [list(map(float, ln.split(","))) for ln in r.stdout.strip().splitlines()[1:]]
+    kw = dict(n=64, q_f=27, q_g=19, forcing="shift", u0=0.05, re=1600.0, fr=0.6, sc=0.7, g_over_n=0.02,
+              noise_amp=1e-6, seed=0, diag_every=25)
+    net = learned.with_gain(learned.Network(z["theta"], z["norm"]), 1.0)
+    sim = stgv.Simulation(device="cuda:0", **kw)
+    sim.set_mlp(net.packed)
+    sim.step(100)
+    recs = sim.diagnostics()
+    plain = stgv.Simulation(device="cuda:0", **kw)
+    plain.step(100)
+    recs_plain = plain.diagnostics()
+    sim.close()
+    plain.close()
+    torch.cuda.synchronize()
+    assert [int(row[0]) for row in rows] == [rec["step"] for rec in recs] == [0, 25, 50, 75]
+    for row, rec in zip(rows, recs):
+        for j, key in enumerate(("ek", "ep", "eps_k", "eps_p", "mass"), start=2):
+            assert row[j] == pytest.approx(rec[key], rel=1e-10, abs=1e-300), (rec["step"], key)
+    # the network did act: the histories leave the plain step's
+    assert rows[-1][4] != pytest.approx(recs_plain[-1]["eps_k"], rel=1e-9)
