@@ -25,7 +25,8 @@
  *    lbm_load_populations synchronise that stream before they return.
  *  - Threading: one host thread per context at a time.
  *  - Determinism: identical parameters give bit-identical populations and
- *    diagnostics (fixed-order FP64 reductions, no atomics).
+ *    diagnostics (fixed-order FP64 reductions, no atomics).  The spectrum of
+ *    lbm_ke_spectrum bins with LDS atomics and is reproducible to rounding.
  *  - Units: lattice units (dx = dt = 1) inside; lbm_diag reports the paper's
  *    non-dimensional values (E / U^2, eps L / U^3, t = step U / L) with
  *    L = n / (2 pi) nodes per unit length and U = u0.
