@@ -12,8 +12,9 @@ Prints ONE JSON line: MLUPS (whole job), ms per step, the roofline of the step
 kernel (algorithmic bytes 2 (Q_f + Q_g) b per node over its HIP-event-timed
 average duration, against the 8 TB/s HBM peak), the streaming-copy ceiling,
 the HBM traffic read from the committed rocprofv3 counter summary when it was
-taken on the current kernel sources, the FP64 oracle timed on the host cores,
-and the energy error of the GPU against the oracle on the 32^3 parity case.
+taken on the current kernel sources, the FP64 oracle timed on the host cores
+(the only part of this script that runs the oracle), and the error of the GPU's
+energy and dissipation histories against the oracle's stored 64^3 histories.
 
 "forms" adds the precision and learned forms: step-kernel throughput of FP16 /
 BF16 weight-shifted storage, of FP64 arithmetic, of every stencil pair and of the
@@ -77,25 +78,30 @@ def cpu_baseline(n, steps, forcing):
                       f"thread, {dt:.1f} s"}
 
 
-def energy_error(stgv, forcing):
-    """Max relative error of E_k, E_p, eps_k, eps_p of the GPU against the oracle on the 32^3 case."""
-    from threadpoolctl import threadpool_limits
+def energy_error(stgv):
+    """Max error of the GPU's E_k, E_p, eps_k, eps_p histories (relative to each history's
+    largest value) against the FP64 oracle's, stored by tests/golden/make_series_64.py (which
+    calls only the oracle): 64^3, velocity shift, Re 1600, Fr 0.5, 2500 steps; for FP32 and
+    FP16 population storage."""
+    import json
 
-    from oracle import model
-    kw = dict(n=32, q_f=27, q_g=19, forcing=forcing, u0=0.05, re=800.0, fr=1.0, sc=1.0,
-              g_over_n=1.0, noise_amp=1e-6, seed=0)
-    with threadpool_limits(limits=1):
-        _, ser = model.run(model.Params(**kw), 201, diag_every=20)
-    sim = stgv.Simulation(diag_every=20, **kw)
-    sim.step(201)
-    recs = sim.diagnostics()
-    sim.close()
-    out = {}
-    for key in ("ek", "ep", "eps_k", "eps_p"):
-        out[key] = max(abs(r[key] - getattr(d, key)) / abs(getattr(d, key))
-                       for r, d in zip(recs, ser) if getattr(d, key) != 0.0)
-    return {"workload": "32^3 D3Q27x19, Re 800, Pr 1, Fr 1, 200 steps, records every 20",
-            **{k: float(f"{v:.3e}") for k, v in out.items()}}
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "series_64_shift.json")))
+    ref = gold["fp64"]
+    out = {"workload": f"{gold['params']['n']}^3 D3Q27x19 velocity shift, Re {gold['params']['re']:g}, "
+                       f"Fr {gold['params']['fr']:g}, Sc {gold['params']['sc']:g}, {gold['steps']} steps, "
+                       f"records every {gold['every']}, against the FP64 oracle's histories "
+                       f"(tests/golden/series_64_shift.json)"}
+    for storage in ("fp32", "fp16"):
+        sim = stgv.Simulation(diag_every=gold["every"], storage=storage, **gold["params"])
+        sim.step(gold["steps"] + 1)
+        recs = sim.diagnostics()
+        sim.close()
+        assert [r["step"] for r in recs] == [d["step"] for d in ref]
+        for key in ("ek", "ep", "eps_k", "eps_p"):
+            top = max(abs(d[key]) for d in ref)
+            err = max(abs(r[key] - d[key]) for r, d in zip(recs, ref)) / top
+            out[key if storage == "fp32" else f"{key}_fp16"] = float(f"{err:.3e}")
+    return out
 
 
 def kernel_time(stgv, stream, kw, steps, warmup, packed=None):
@@ -344,7 +350,7 @@ def main():
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_n, args.cpu_sample_steps, args.forcing)
         out["cpu_baseline"]["host_threads_available"] = os.cpu_count()
     if not args.no_energy_error:
-        out["energy_error"] = energy_error(stgv, args.forcing)
+        out["energy_error"] = energy_error(stgv)
     if not args.no_forms:
         out["forms"] = forms(stgv, stream, args.forms_t, K, W)
     print(json.dumps(out), flush=True)
