@@ -182,3 +182,17 @@ def test_driver_runs_the_learned_step_like_the_binding(tmp_path):
             assert row[j] == pytest.approx(rec[key], rel=1e-10, abs=1e-300), (rec["step"], key)
     # the network did act: the histories leave the plain step's
     assert rows[-1][4] != pytest.approx(recs_plain[-1]["eps_k"], rel=1e-9)
+
+
+def test_learned_driver_exports_the_shipped_network(tmp_path, capsys):
+    import numpy as np
+
+    from paper_2605_14505_amd import learned
+
+    out = tmp_path / "net.bin"
+    learned.main(["--export", str(out), "--gain", "0.5"])
+    assert "gain 0.5" in capsys.readouterr().out
+    z = np.load(os.path.join(ROOT, "paper_2605_14505_amd", "data", "learned64.npz"), allow_pickle=False)
+    body = np.frombuffer(out.read_bytes()[16:], dtype="<f4")
+    np.testing.assert_array_equal(body[:learned.NPARAM], z["theta"].astype(np.float32))
+    np.testing.assert_allclose(body[learned.NPARAM + 94:], (z["norm"][94:] * 0.5).astype(np.float32))
