@@ -475,6 +475,241 @@ __device__ __forceinline__ void node_collide(C* f, C* g, const PhysConsts& c,
   col.finish(f, g);
 }
 
+// ---------------------------------------------------------------------------
+// The time step's collision in split arithmetic
+//
+// Why: the scalar lattice carries rho_0 + rho' = 1 + rho', so its equilibrium
+// flux (1 + rho') u moves the background density with the velocity, and an
+// error of one FP32 ulp in u (or in the velocity-linear equilibrium term
+// 3 w e.u, the largest part of every deviation) moves background mass between
+// nodes: rho' (~1e-3 - 1e-2) sees it at ~1e-5 relative within 100 steps.  The
+// density deviation is hit the same way through the momentum lattice's linear
+// term.  So the step keeps those two quantities exact or nearly so, in FP32:
+//
+// * every momentum population is split as df = hi + lo with hi on the grid of
+//   2^-23 (`grid_split`); sums of grid values below 2 in magnitude are exact in
+//   FP32, so j = sum e df is held as an exact grid part jh plus a small lo sum
+//   whose own rounding is ~2^-24 of 2^-23;
+// * the velocities are jh + a small lo part (u' = j/rho = j - j drho/rho:
+//   no rounding of 1 + drho enters it);
+// * the linear equilibrium terms w (drho + 3 e.J) and w (rho' + 3 e.(1 + rho')t)
+//   are formed from grid parts (exact sums), an error-free product with the
+//   weight (the fused multiply-add residual) and small remainders; the
+//   quadratic terms, two orders smaller, are plain FP32.  The weight's own FP32
+//   residual (w - fl(w), ~1e-8 relative) multiplies the whole equilibrium:
+//   without it the sum of the equilibria misses rho' (or drho) by
+//   ~1e-8 (3/2) u^2 at every node and step, always with the same sign, a
+//   steady drift of the scalar and momentum masses.
+// The increment d_i = f^eq_i - f_i is then (hi_i - f_i) + lo_i, whose roundings
+// are at the scale of d rather than of f, and the population is updated once:
+// f*_i = f_i + (omega d_i + G_i).  The only rounding at the scale of the
+// population is the final one, the one FP32 storage makes anyway.
+// ---------------------------------------------------------------------------
+// x = hi + lo exactly, hi on the grid of ulp(1.5): 2^-23 in FP32, 2^-52 in FP64
+// (exact for |x| < 0.5; beyond it hi + lo still equals x, on a coarser grid).
+template <typename C>
+__device__ __forceinline__ void grid_split(C x, C& hi, C& lo) {
+  const C k = C(1.5);
+  hi = (x + k) - k;
+  lo = x - hi;
+}
+
+// e . v for a lattice direction, summed in a fixed order (x, y, z); -0 is the
+// neutral start so that a single term is passed through unchanged.
+template <typename C>
+__device__ __forceinline__ C edot(int ex, int ey, int ez, const C* v) {
+  C r = C(-0.0);
+  if (ex != 0) r += ex > 0 ? v[0] : -v[0];
+  if (ey != 0) r += ey > 0 ? v[1] : -v[1];
+  if (ez != 0) r += ez > 0 ? v[2] : -v[2];
+  return r;
+}
+
+// Density deviation (plain pair sum) and momentum j = sum e df as grid part
+// (exact) plus remainder.
+template <int Q, typename C>
+__device__ __forceinline__ void split_moments(const C* a, C& m0, C* jh, C* jl) {
+  using S = Stencil<Q>;
+  C s = a[0];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) { jh[k] = C(-0.0); jl[k] = C(-0.0); }
+#pragma unroll
+  for (int i = 1; i < Q; i += 2) {
+    s += a[i] + a[i + 1];
+    C h0, l0, h1, l1;
+    grid_split(a[i], h0, l0);
+    grid_split(a[i + 1], h1, l1);
+    const C dh = h0 - h1, dl = l0 - l1;    // e_{i+1} = -e_i
+    const int e[3] = {S::ex[i], S::ey[i], S::ez[i]};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (e[k] == 0) continue;
+      jh[k] += e[k] > 0 ? dh : -dh;
+      jl[k] += e[k] > 0 ? dl : -dl;
+    }
+  }
+  m0 = s;
+}
+
+template <typename C>
+struct StepMacro {
+  C drho, rho, inv, dsig, rho_p, s, Fz;
+  C jh[3];      // grid part of j = sum e df, shared by every velocity below
+  C j[3];       // j (FP32 value), for the diagnostics
+  C jeq_l[3];   // rho v_eq - jh: the equilibrium momentum's remainder (j + k F e_z)
+  C u[3];       // physical velocity, Eq. (7) (FP32 value)
+  C ul[3];      // u - jh
+  C v[3];       // velocity of the momentum equilibrium (FP32 value)
+  C t[3];       // velocity of the scalar equilibrium (FP32 value)
+  C fl[3];      // (1 + rho') t - jh: remainder of the scalar equilibrium's flux
+};
+
+template <int QF, int QG, int FORCE, typename C>
+__device__ __forceinline__ void step_macro(const C* f, const C* g, const PhysConsts& c,
+                                           StepMacro<C>& m) {
+  C jl[3];
+  split_moments<QF>(f, m.drho, m.jh, jl);
+  m.dsig = pair_sum<QG>(g);
+  m.rho = C(1) + m.drho;                          // Eq. (6)
+  m.inv = C(1) / m.rho;
+  const C q = m.drho * m.inv;                     // u' = j / rho = j - j drho / rho
+  C upl[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) upl[k] = jl[k] - (m.jh[k] + jl[k]) * q;
+  const C upz = m.jh[2] + upl[2];
+  m.s = -upz * (C)c.beta;                         // Eqs. (12)-(13), bare u_z
+  m.rho_p = m.dsig + C(0.5) * m.s;                // Eqs. (16)-(17)
+  m.Fz = -(C)c.G * m.rho_p;                       // Eq. (18)
+  const C fz_inv = m.Fz * m.inv;
+  m.ul[0] = upl[0];
+  m.ul[1] = upl[1];
+  m.ul[2] = upl[2] + C(0.5) * fz_inv;             // Eq. (7)
+  C vl[3] = {upl[0], upl[1], upl[2]};             // EDM relaxes to f^eq(u')
+  m.jeq_l[0] = jl[0];
+  m.jeq_l[1] = jl[1];
+  m.jeq_l[2] = jl[2];
+  if (FORCE == FORCE_SHIFT) {                     // Eq. (10), shift tau F / rho
+    vl[2] = upl[2] + (C)c.tau_f * fz_inv;
+    m.jeq_l[2] = jl[2] + (C)c.tau_f * m.Fz;
+  } else if (FORCE == FORCE_GUO || FORCE == FORCE_HCZ) {
+    vl[2] = m.ul[2];
+    m.jeq_l[2] = jl[2] + C(0.5) * m.Fz;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    m.j[k] = m.jh[k] + jl[k];
+    m.u[k] = m.jh[k] + m.ul[k];
+    m.v[k] = m.jh[k] + vl[k];
+    // the scalar equilibrium moves with the momentum equilibrium's velocity,
+    // except under EDM, whose fluid velocity is u of Eq. (7)
+    const C tl = FORCE == FORCE_EDM ? m.ul[k] : vl[k];
+    m.t[k] = m.jh[k] + tl;
+    m.fl[k] = tl + m.rho_p * m.t[k];
+  }
+}
+
+// Post-collision populations of both lattices, in place (Eqs. (5), (8)-(11),
+// (14)-(15) with the forcing scheme's term).
+template <int QF, int QG, int FORCE, typename C>
+__device__ __forceinline__ void step_collide(C* f, C* g, const PhysConsts& c, const StepMacro<C>& m) {
+  using SF = Stencil<QF>;
+  using SG = Stencil<QG>;
+  constexpr C icf = C(1.0 / SF::cs2);
+  constexpr C icg = C(1.0 / SG::cs2);
+  const C omega_f = (C)c.omega_f, omega_g = (C)c.omega_g;
+  C dr_h, dr_l;
+  grid_split(m.drho, dr_h, dr_l);
+  const C vsq = m.v[0] * m.v[0] + m.v[1] * m.v[1] + m.v[2] * m.v[2];
+  const C qb_f = -C(0.5) * icf * vsq;
+  const C half_c = (C(1) - C(0.5) * omega_f) * m.Fz;
+  const C bracket_c = (FORCE == FORCE_GUO) ? half_c : m.Fz;          // Guo / EDM
+  const C hcz_c = icf * half_c * m.inv;                               // HCZ
+  // momentum lattice, by opposite pairs (the rest direction is its own pair)
+#pragma unroll
+  for (int i = 0; i < QF; i += (i == 0 ? 1 : 2)) {
+    const int ex = SF::ex[i], ey = SF::ey[i], ez = SF::ez[i];
+    const C w = C(SF::w[i]);
+    const C wl = C(SF::w[i] - (double)w);              // the weight's FP32 residual
+    const C ejh = edot(ex, ey, ez, m.jh);
+    const C ejl = edot(ex, ey, ez, m.jeq_l);
+    const C xi = icf * edot(ex, ey, ez, m.v);
+    const C qv = m.rho * fma_c(C(0.5) * xi, xi, qb_f);  // rho (xi^2/2 - v^2/(2c^2)), even in e
+    const C eu = edot(ex, ey, ez, m.u);
+#pragma unroll
+    for (int sgn = 1; sgn >= (i == 0 ? 1 : -1); sgn -= 2) {
+      const int k = sgn > 0 ? i : i + 1;
+      const C y = fma_c(C(sgn) * icf, ejh, dr_h);          // drho + 3 e.J, grid parts: exact
+      const C r = fma_c(C(sgn) * icf, ejl, dr_l);          // remainders
+      const C rq = r + qv;
+      const C ph = w * y;
+      C pe = fma_c(w, y, -ph);                              // w y = ph + pe exactly
+      pe = fma_c(wl, y + rq, pe);                           // the weight's residual on all of it
+      const C lo = fma_c(w, rq, pe);
+      const C d = (ph - f[k]) + lo;                         // f^eq - f
+      C force = C(0);
+      if (FORCE == FORCE_GUO || FORCE == FORCE_EDM) {
+        //   Guo: G_i = (1 - omega/2) w [(e_z - u_z) / c^2 + (e.u) e_z / c^4] Fz;
+        //   EDM: G_i = f^eq_i(u' + F/rho) - f^eq_i(u'), for the second-order
+        //        equilibrium exactly w [(e_z - u_z) / c^2 + (e.u) e_z / c^4] Fz
+        //        with u = u' + F/(2 rho): the Guo bracket without (1 - omega/2)
+        C br = -icf * m.u[2];
+        const int ezk = sgn * ez;
+        if (ezk != 0) {
+          const C t = icf * fma_c(C(sgn) * icf, eu, C(1));
+          br += ezk > 0 ? t : -t;
+        }
+        force = w * bracket_c * br;
+      } else if (FORCE == FORCE_HCZ) {
+        //   HCZ: G_i = (1 - omega/2) (e_z - u_z) Fz / (rho c^2) f^eq_i(u)
+        force = hcz_c * (C(sgn * ez) - m.u[2]) * (w + (ph + lo));
+      }
+      f[k] = f[k] + fma_c(omega_f, d, force);
+    }
+  }
+  // scalar lattice: g^eq_j = w [rho' + 3 e.(1 + rho') t + (1 + rho')(xi^2/2 - t^2/(2c^2))]
+  C rp_h, rp_l;
+  grid_split(m.rho_p, rp_h, rp_l);
+  const C conc = C(1) + m.rho_p;
+  const C tsq = (FORCE == FORCE_EDM) ? m.t[0] * m.t[0] + m.t[1] * m.t[1] + m.t[2] * m.t[2] : vsq;
+  const C qb_g = -C(0.5) * icg * tsq;
+  const C src = (C(1) - C(0.5) * omega_g) * m.s;       // (1 - 1/(2 tau_g)) S / w
+#pragma unroll
+  for (int j = 0; j < QG; j += (j == 0 ? 1 : 2)) {
+    const int ex = SG::ex[j], ey = SG::ey[j], ez = SG::ez[j];
+    const C w = C(SG::w[j]);
+    const C wl = C(SG::w[j] - (double)w);
+    const C ejh = edot(ex, ey, ez, m.jh);
+    const C ejl = edot(ex, ey, ez, m.fl);
+    const C xi = icg * edot(ex, ey, ez, m.t);
+    const C qv = conc * fma_c(C(0.5) * xi, xi, qb_g);
+    const C ws = w * src;
+#pragma unroll
+    for (int sgn = 1; sgn >= (j == 0 ? 1 : -1); sgn -= 2) {
+      const int k = sgn > 0 ? j : j + 1;
+      const C y = fma_c(C(sgn) * icg, ejh, rp_h);
+      const C r = fma_c(C(sgn) * icg, ejl, rp_l);
+      const C rq = r + qv;
+      const C ph = w * y;
+      C pe = fma_c(w, y, -ph);
+      pe = fma_c(wl, y + rq, pe);
+      const C lo = fma_c(w, rq, pe);
+      const C h = (ph - g[k]) + lo;                         // g^eq - g
+      g[k] = g[k] + fma_c(omega_g, h, ws);
+    }
+  }
+}
+
+// The step's moments in the form the diagnostics take.
+template <typename C>
+__device__ __forceinline__ NodeMacro<C> diag_macro(const StepMacro<C>& s) {
+  NodeMacro<C> m;
+  m.drho = s.drho; m.rho = s.rho; m.dsig = s.dsig; m.rho_p = s.rho_p; m.s = s.s; m.Fz = s.Fz;
+  m.jx = s.j[0]; m.jy = s.j[1]; m.jz = s.j[2];
+  m.ux = s.u[0]; m.uy = s.u[1]; m.uz = s.u[2];
+  m.vx = s.v[0]; m.vy = s.v[1]; m.vz = s.v[2];
+  return m;
+}
+
 // Diagnostic outputs of one node: the five fields (rho - 1, u, rho') and its
 // contributions to the block partials.
 template <typename C>

@@ -77,11 +77,21 @@ def storage_floor(kw, steps, storage):
     return field_errors(rounded, exact)
 
 
-# Tolerance = max(1e-5, K x storage floor).  With FP64 arithmetic the GPU adds only its
-# own storage rounding, so its error is the floor up to the luck of the rounding (K = 2.5).
-# With FP32 arithmetic every collision adds roundings of the velocity-carrying
-# deviations (ulp(0.05) ~ 4e-9) to the non-conserved moments, measured at 3-6x the floor.
-K_ARITH = {"fp64": 2.5, "fp32": 8.0}
+# Every field within 1e-5 (the stated bar) and within K x the storage floor.  With FP64
+# arithmetic the GPU adds only its own storage rounding, so its error is the floor up to
+# the luck of the rounding.  The FP32 step keeps the velocity-linear equilibrium terms and
+# the momentum sums exact (split arithmetic, lbm_device.hpp), so its only rounding at the
+# scale of a population is the store's: measured at 1.0-1.6 x the floor.
+K_FLOOR = 2.0
+BAR = 1e-5
+
+
+def scalar_floor_above_bar(q_g):
+    # D3Q7 and D3Q15 scalar deviations carry the background advection w (1/c^2) e.u with
+    # larger weights (1/8 at c^2 = 1/4; 1/9) than D3Q19 (1/18): one FP32 rounding of them
+    # is ~3x larger against rho', and the FP32-storage floor of rho' after 100 steps is
+    # 1.2-2.5e-5 even with FP64 arithmetic.  Those pairs are held to their floor.
+    return q_g in (7, 15)
 
 
 def gpu_sim(**kw):
@@ -131,10 +141,9 @@ def test_tgv_parity_32(forcing, compute):
     print(f"\n{forcing} {compute}: 100 steps {e100}\n  fp32-storage floor {f100}"
           f"\n{forcing} {compute}: 200 steps {e200}\n  fp32-storage floor {f200}")
     for k in FIELDS:
-        assert e100[k] <= max(1e-5, K_ARITH[compute] * f100[k]), (k, e100[k], f100[k])
-        assert e200[k] <= max(1e-5, K_ARITH[compute] * f200[k]), (k, e200[k], f200[k])
-        if compute == "fp64":
-            assert e100[k] <= 1e-5, (k, e100[k])
+        assert e100[k] <= BAR and e200[k] <= BAR, (k, e100[k], e200[k])
+        assert e100[k] <= K_FLOOR * f100[k] + 1e-7, (k, e100[k], f100[k])
+        assert e200[k] <= K_FLOOR * f200[k] + 1e-7, (k, e200[k], f200[k])
 
 
 @pytest.mark.parametrize("q_f,q_g,forcing", [(27, 7, "guo"), (19, 7, "shift"), (27, 7, "shift"),
@@ -152,7 +161,9 @@ def test_other_stencil_pairs_parity(q_f, q_g, forcing, compute):
     floor = storage_floor(kw, 100, "fp32")
     print(f"\n{q_f}x{q_g} {forcing} {compute} 100 steps {e}\n  fp32-storage floor {floor}")
     for k in FIELDS:
-        assert e[k] <= max(1e-5, K_ARITH[compute] * floor[k]), (k, e[k], floor[k])
+        assert e[k] <= K_FLOOR * floor[k] + 1e-7, (k, e[k], floor[k])
+        if not scalar_floor_above_bar(q_g):
+            assert e[k] <= BAR, (k, e[k])
 
 
 @pytest.mark.parametrize("storage", ["fp16", "bf16"])
@@ -295,6 +306,16 @@ def test_diagnostic_series_against_oracle(forcing):
         # sums of n^3 FP32 moments: ~1e-10 relative
         assert r["mass"] == pytest.approx(d.mass, rel=1e-9)
         assert r["scalar"] == pytest.approx(d.scalar, rel=1e-9)
+        # the scalar perturbation itself (sum of rho' - 1e-4 here - over the box): the step's
+        # scalar budget per node is exact up to roundings at the scale of its deviations
+        # (~1e-9), not mirror-symmetric, so the box total wanders by ~1e-6 over the first tens
+        # of steps; a budget bias of the collision (e.g. an FP32 weight residual left in the
+        # equilibria: ~1e-11 per node and step, one sign) would grow like n^3 steps instead
+        n3 = kw["n"] ** 3
+        dpert = abs((r["scalar"] - n3) - (d.scalar - n3))
+        print(f"step {r['step']}: scalar perturbation gpu {r['scalar'] - n3:.4e} "
+              f"oracle {d.scalar - n3:.4e} diff {dpert:.2e}")
+        assert dpert <= 2e-10 * n3
         assert r["umax"] == pytest.approx(d.umax, rel=1e-5)
         assert r["nonfinite"] == 0
 
@@ -478,23 +499,24 @@ def test_maximum_box_1024_fp16_sampled_parity():
 # ---------------------------------------------------------------------------
 # degenerate cases: no stratification, no steps
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("compute", ["fp32", "fp64"])
 @pytest.mark.parametrize("forcing", ["guo", "shift"])
-def test_unstratified_parity_and_zero_potential_energy(forcing):
+def test_unstratified_parity_and_zero_potential_energy(forcing, compute):
     # Fr = inf: G = 0, no buoyancy acts and the scalar is a passive tracer of the 1e-6
     # noise, so rho' is tiny against the FP32 rounding of the velocity terms its lattice
-    # stores; the bar is that of the other parity cases, max(1e-5, 2.5 x the oracle's own
-    # error with FP32 storage).  E_p and eps_p are exactly zero.
+    # stores; the bar is max(1e-5, K_FLOOR x the oracle's own error with FP32 storage).
+    # E_p and eps_p are exactly zero.
     kw = c1_kw(fr=math.inf, forcing=forcing)
     ref = oracle_fields_series(tuple(sorted(kw.items())), (100,))
     floor = storage_floor(kw, 100, "fp32")
-    sim = gpu_sim(compute="fp64", diag_every=50, **kw)
+    sim = gpu_sim(compute=compute, diag_every=50, **kw)
     sim.step(100)
     err = field_errors(sim.fields().cpu().numpy(), ref[100])
     recs = sim.diagnostics()
     sim.close()
     print(f"\nunstratified {forcing}: {err}\n  fp32-storage floor {floor}")
     for k in FIELDS:
-        assert err[k] <= max(1e-5, K_ARITH["fp64"] * floor[k]), (k, err[k], floor[k])
+        assert err[k] <= max(BAR, K_FLOOR * floor[k]), (k, err[k], floor[k])
     assert [r["step"] for r in recs] == [0, 50]
     assert all(r["ep"] == 0.0 and r["eps_p"] == 0.0 for r in recs)
     assert all(r["ek"] > 0.0 and r["eps_k"] > 0.0 for r in recs)
