@@ -155,3 +155,65 @@ def test_conserved_feature_slots_are_the_full_moments(forcing):
     np.testing.assert_allclose(x[3], -0.5 * fz if forcing == "guo" else -U.tau_f * fz, rtol=1e-9)
     np.testing.assert_allclose(x[27], -0.5 * m.s, rtol=1e-9, atol=1e-18)
     assert np.abs(x[3]).max() > 0 and np.all(x[0:3] == 0.0)
+
+
+def test_restriction_rescales_a_relaxed_shear_wave_to_the_coarse_run():
+    # A shear wave u_x = U sin z relaxes on the fine grid (32^3, tau_f = 1) and on the
+    # coarse grid (8^3, the same physical viscosity, so tau_c = 0.625) from equilibrium.
+    # After the same physical time (64 fine, 16 coarse steps) the restricted fine state
+    # must carry the coarse run's own non-equilibrium shear stress Pi_xz: the lattice
+    # gradient is 4 x larger on the coarse grid and Pi_neq ~ tau c_s^2 du, hence the
+    # rescale 4 tau_c / tau_f (2.5 here).  Without it the stress is 0.40 of the coarse
+    # run's; with 4 alone, tau_c / tau_f alone or the inverted ratio it is off by a
+    # factor 1.6, 0.25 or 2.6.  Measured agreement: 0.8 %.
+    lf, lg = lat.D3Q27, lat.D3Q19
+    u0, nf, nc, tau_f = 0.05, 32, 8, 1.0
+    re = u0 * (nf / (2 * math.pi)) / ((tau_f - 0.5) / 3.0)
+    pf = model.Params(n=nf, forcing="guo", u0=u0, re=re, fr=math.inf, sc=1.0)
+    pc = model.Params(n=nc, forcing="guo", u0=u0, re=re, fr=math.inf, sc=1.0)
+    assert model.units(pf).tau_f == pytest.approx(1.0) and model.units(pc).tau_f == pytest.approx(0.625)
+
+    def shear(p):
+        z = 2 * math.pi * np.arange(p.n) / p.n
+        u = np.zeros((3, p.n, p.n, p.n))
+        u[0] = u0 * np.sin(z)[:, None, None]
+        return model.f_equilibrium(lf, np.ones((p.n,) * 3), u), model.theta(lg, u)
+
+    def stress_amplitude(f, g, p):
+        m = model.macro(f, g, lf, lg, model.units(p))
+        neq = f - model.f_equilibrium(lf, m.rho, m.u)
+        pi = np.tensordot((lf.e[:, 0] * lf.e[:, 2]).astype(float), neq, axes=(0, 0))
+        z = 2 * math.pi * np.arange(p.n) / p.n
+        return 2.0 * np.mean(pi * np.cos(z)[:, None, None])
+
+    (ff, gf), _ = model.run(pf, 64, state=shear(pf))
+    (fc, gc), _ = model.run(pc, 16, state=shear(pc))
+    fr, gr = L.restrict(ff, gf, pf, pc)
+    ratio = stress_amplitude(fr, gr, pc) / stress_amplitude(fc, gc, pc)
+    assert abs(ratio - 1.0) < 0.05, ratio
+
+
+def test_forward_pass_of_a_hand_computed_network():
+    # Two rows through a network with a handful of non-zero weights, worked out with
+    # scalar tanh: tanh on both hidden layers, none on the output, W rows index outputs.
+    p = {name: np.zeros(shape) for name, shape in L.SHAPES}
+    p["W1"][0, 0], p["b1"][1] = 0.5, -0.25
+    p["W1"][2, 46], p["W1"][2, 3] = 1.0, 0.5
+    p["W2"][0, 0], p["W2"][0, 1], p["b2"][0] = 1.0, 2.0, 0.1
+    p["W2"][1, 0], p["W2"][1, 2] = -1.0, 0.75
+    p["W3"][0, 0], p["W3"][0, 1], p["b3"][0] = 3.0, 1.0, 2.0
+    p["W3"][40, 1], p["b3"][7] = -2.0, -0.3
+    x = np.zeros((2, L.N_IN))
+    x[0, 0] = 1.0
+    x[1, 46], x[1, 3], x[1, 0] = 2.0, -1.0, -2.0
+    out, _ = L.forward(L.pack(p), x)
+    th = math.tanh
+    for r in range(2):
+        h1 = [th(0.5 * x[r, 0]), th(-0.25), th(x[r, 46] + 0.5 * x[r, 3])]
+        h2 = [th(h1[0] + 2.0 * h1[1] + 0.1), th(-h1[0] + 0.75 * h1[2])]
+        want = np.zeros(L.N_OUT)
+        want[0] = 3.0 * h2[0] + h2[1] + 2.0
+        want[40] = -2.0 * h2[1]
+        want[7] = -0.3
+        assert np.allclose(out[r], want, rtol=0, atol=1e-15), (r, out[r][[0, 7, 40]], want[[0, 7, 40]])
+    assert abs(out[0, 0]) > 1.5          # large enough that a tanh on the output would show

@@ -165,3 +165,90 @@ def test_unstratified_limit_decouples_the_scalar():
     (f1, _), _ = model.run(model.Params(q_g=19, **base), 5)
     (f2, _), _ = model.run(model.Params(q_g=7, **base), 5)
     np.testing.assert_array_equal(f1, f2)
+
+
+# ---------------------------------------------------------------------------
+# potential energy and its dissipation on a prescribed density perturbation
+# (Section 3.2, Eq. (23); Section 3.3, Eq. (26))
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("m_x,m_z", [(1, 1), (2, 3)])
+def test_potential_energy_and_dissipation_closed_forms(m_x, m_z):
+    # rho' = A cos(k_x x) cos(k_z z) on the nodes, fluid at rest.  Discrete orthogonality
+    # gives <rho'^2> = A^2 / 4, so E_p = (G/N)^2 A^2 / 8; the periodic central difference
+    # of cos(k x) is -sin(k) sin(k x), so <|grad rho'|^2> = A^2 (sin^2 k_x + sin^2 k_z) / 4
+    # and eps_p = D (G/N)^2 A^2 (sin^2 k_x + sin^2 k_z) / 4 (lattice units, k per node).
+    # G/N = 0.3 and N = 0.01 make G = 0.003 distinct from G/N, and Sc = 0.7 makes D
+    # distinct from nu: squaring G/N wrongly, using G for G/N, or dropping D fails.
+    n, amp, g_over_n = 24, 3e-3, 0.3
+    p = model.Params(n=n, u0=0.05, re=400.0, fr=1.0, sc=0.7, g_over_n=g_over_n)
+    U = dataclasses.replace(model.units(p), nb=0.01, G=g_over_n * 0.01)
+    j = np.arange(n)
+    Z, Y, X = np.meshgrid(j, j, j, indexing="ij")
+    kx, kz = 2 * math.pi * m_x / n, 2 * math.pi * m_z / n
+    rho_p = amp * np.cos(kx * X) * np.cos(kz * Z)
+    zero = np.zeros((3, n, n, n))
+    m = model.Macro(rho=np.ones((n, n, n)), up=zero, sigma=rho_p + 1.0, s=np.zeros((n, n, n)),
+                    rho_p=rho_p, F=zero, u=zero, ueq=zero, utheta=zero)
+    d = model.diagnostics(m, U, 0)
+    ep = g_over_n ** 2 * amp ** 2 / 8.0
+    eps_p = U.D * g_over_n ** 2 * amp ** 2 * (math.sin(kx) ** 2 + math.sin(kz) ** 2) / 4.0
+    assert d.ep * U.u0 ** 2 == pytest.approx(ep, rel=1e-12)
+    assert d.eps_p * U.u0 ** 3 / U.L == pytest.approx(eps_p, rel=1e-12)
+    assert d.ek == 0.0 and d.eps_k == 0.0
+
+
+# ---------------------------------------------------------------------------
+# the initial pressure, Eq. (21), as read
+# ---------------------------------------------------------------------------
+def _poisson_pressure(u, h):
+    """Pressure of an incompressible velocity field on the periodic box: the solution of
+    lap p = -rho_0 d_i u_j d_j u_i with zero mean, all derivatives spectral."""
+    n = u.shape[-1]
+    k = np.fft.fftfreq(n, d=h) * 2 * math.pi
+    KZ, KY, KX = np.meshgrid(k, k, k, indexing="ij")
+    K = (KX, KY, KZ)
+    uh = [np.fft.fftn(c) for c in u]
+    du = [[np.real(np.fft.ifftn(1j * K[i] * uh[j])) for j in range(3)] for i in range(3)]   # du[i][j] = d_i u_j
+    rhs = -model.RHO0 * sum(du[i][j] * du[j][i] for i in range(3) for j in range(3))
+    k2 = KX ** 2 + KY ** 2 + KZ ** 2
+    k2[0, 0, 0] = 1.0
+    ph = -np.fft.fftn(rhs) / k2
+    ph[0, 0, 0] = 0.0
+    return np.real(np.fft.ifftn(ph))
+
+
+def test_initial_pressure_solves_the_taylor_green_poisson_equation():
+    # The paper's Eq. (21) prints the z factor garbled as cos(2z + 2); the reading
+    # (cos 2x + cos 2y)(cos 2z + 2) U^2 / 16 is the pressure of the initial velocity of
+    # Eq. (20).  The spectral Poisson solution of lap p = -rho_0 d_i u_j d_j u_i must equal
+    # it to rounding (up to the constant a Poisson solution leaves free); the printed form
+    # must not.
+    n, u0 = 32, 0.05
+    u, p0 = model.tgv_fields(n, u0)
+    p = _poisson_pressure(u, 2 * math.pi / n)
+    read = p0 - p0.mean()
+    assert np.abs(p - read).max() <= 1e-13 * np.abs(read).max() + 1e-18
+    j = np.arange(n)
+    Z, Y, X = np.meshgrid(j, j, j, indexing="ij")
+    x, y, z = (2 * math.pi / n * a for a in (X, Y, Z))
+    printed = model.RHO0 * u0 ** 2 / 16.0 * (np.cos(2 * x) + np.cos(2 * y)) * np.cos(2 * z + 2)
+    printed -= printed.mean()
+    assert np.abs(p - printed).max() > 0.3 * np.abs(read).max()
+
+
+# ---------------------------------------------------------------------------
+# -dE/dt of the energy history (Section 3.1: second-order central differences in time)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("a,dt", [(0.3, 0.05), (1.0, 0.02)])
+def test_dissipation_series_of_an_exponential_decay(a, dt):
+    # E = exp(-a t): the central difference gives -dE/dt = a exp(-a t) sinh(a dt) / (a dt),
+    # a relative error (a dt)^2 / 6 + O((a dt)^4), at the interior times t_1 .. t_{m-2}.
+    # A forward difference (error a dt / 2), a sign slip or a wrong denominator fail.
+    ts = np.arange(0.0, 10.0, dt)
+    t, rate = model.dissipation_series(ts, np.exp(-a * ts))
+    assert np.array_equal(t, ts[1:-1])
+    exact = a * np.exp(-a * t)
+    rel = rate / exact - 1.0
+    x = a * dt
+    assert np.allclose(rel, math.sinh(x) / x - 1.0, rtol=1e-6, atol=1e-12)
+    assert 0.9 * x * x / 6 < rel.max() < 1.1 * x * x / 6
