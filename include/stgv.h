@@ -55,9 +55,9 @@ typedef enum {
 typedef enum {
   LBM_FORCE_GUO = 0,   /* Guo-Zheng-Shi discrete source term (cited with Eq. (5)) */
   LBM_FORCE_SHIFT = 1, /* Shan-Chen velocity shift u_eq = u' + tau_f F / rho (Eq. (10)) */
-  LBM_FORCE_EDM = 2,   /* exact difference method (Kupershtokh), compared in Section 4:
+  LBM_FORCE_EDM = 2,   /* exact difference method (Kupershtokh), compared in Section 3.6:
                           relax to f^eq(u'), add f^eq(u' + F/rho) - f^eq(u') */
-  LBM_FORCE_HCZ = 3    /* He-Shan-Doolen source term, compared in Section 4: relax to
+  LBM_FORCE_HCZ = 3    /* He-Shan-Doolen source term, compared in Section 3.6: relax to
                           f^eq(u), add (1 - 1/2tau)(e - u).F/(rho c_s^2) f^eq(u) */
 } lbm_forcing;
 
@@ -242,7 +242,7 @@ int lbm_training_pairs(lbm_ctx* coarse, const float* a_dev, const float* b_dev, 
 int lbm_set_mlp(lbm_ctx* ctx, const void* packed_dev);
 
 /* ------------------------------------------------------------------------
- * Post-processing (Section 4): the quantities derived from the diagnostic
+ * Post-processing (Sections 3.4-3.5): the quantities derived from the diagnostic
  * histories and the kinetic-energy spectrum.  Physical units (U = L = 1 on the
  * 2 pi box): nu = 1/Re, N = 1/Fr.
  * ------------------------------------------------------------------------ */

@@ -9,7 +9,7 @@ against the paper's Section 2:
   tau_f = nu/c_s^2 + 1/2, equilibrium Eq. (9);
 * forcing: the Guo et al. discrete source term (cited with Eq. (5), formula not
   printed in the paper) or the Shan-Chen velocity shift Eq. (10); and the two other
-  schemes of the forcing comparison (Section 4), cited there without formulas: the
+  schemes of the forcing comparison (Section 3.6), cited there without formulas: the
   exact difference method (EDM) of Kupershtokh and the He-Shan-Doolen ("HCZ")
   source term;
 * scalar lattice: LBE Eq. (11) with the stratification source Eqs. (12)-(13),

@@ -4,8 +4,8 @@ derives from the energy and dissipation histories and from the velocity field.
 Test infrastructure only (part of the CPU oracle).  Definitions, in the paper's
 physical units (U = L = 1 on the 2 pi box, so nu = 1/Re and N = 1/Fr):
 
-* buoyancy Reynolds number R = eps_k / (nu N^2)  (Section 4, buoyancy Reynolds number);
-* flux coefficient Gamma = eps_p / eps_k  (Section 4, mixing);
+* buoyancy Reynolds number R = eps_k / (nu N^2)  (Section 3.4, buoyancy Reynolds number);
+* flux coefficient Gamma = eps_p / eps_k  (Section 3.5, Froude number effects);
 * bulk flux coefficient Gamma_b = int_0^T eps_p dt / int_0^T eps_k dt, T = 30;
 * turbulent Froude number Fr_t = int_0^T eps_k dt / (N int_0^T E_k dt);
 * kinetic-energy spectrum E(k) = sum over integer wavevectors with round(|k|) = k of

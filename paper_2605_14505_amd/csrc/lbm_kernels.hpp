@@ -98,6 +98,24 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
   return z ^ (z >> 31);
 }
 
+// One rounding of an FP64 value into the storage type.  FP32 rounds directly; FP16 and
+// BF16 go through FP32 rounded to odd (truncate, then set the last bit when inexact),
+// which carries at least two more significand bits than either, so the final
+// round-to-nearest-even of the hardware conversion equals a direct rounding of the
+// FP64 value.
+__device__ __forceinline__ float round_to_odd_f32(double d) {
+  float r = (float)d;
+  if ((double)r != d) {
+    uint32_t b = __float_as_uint(r);
+    if (fabs((double)r) > fabs(d)) b -= 1u;     // step back toward zero (sign-magnitude)
+    r = __uint_as_float(b | 1u);
+  }
+  return r;
+}
+__device__ __forceinline__ void store_once(float* p, double d) { store_as(p, (float)d); }
+__device__ __forceinline__ void store_once(_Float16* p, double d) { store_as(p, round_to_odd_f32(d)); }
+__device__ __forceinline__ void store_once(bf16_t* p, double d) { store_as(p, round_to_odd_f32(d)); }
+
 template <int QF, int QG, typename T>
 __global__ __launch_bounds__(256) void lbm_init_tgv_kernel(T* pop, Geometry geo, double u0,
                                                            double noise_amp, uint64_t seed) {
@@ -126,14 +144,14 @@ __global__ __launch_bounds__(256) void lbm_init_tgv_kernel(T* pop, Geometry geo,
     const double eu = SF::ex[i] * vx + SF::ey[i] * vy + SF::ez[i] * vz;
     const double d = SF::w[i] * (drho + rho * (eu / SF::cs2 + eu * eu / (2.0 * SF::cs2 * SF::cs2)
                                                - usq / (2.0 * SF::cs2)));
-    store_as(pop + (int64_t)i * geo.stride + node, (float)d);
+    store_once(pop + (int64_t)i * geo.stride + node, d);
   }
 #pragma unroll
   for (int j = 0; j < QG; ++j) {
     const double eu = SG::ex[j] * vx + SG::ey[j] * vy + SG::ez[j] * vz;
     const double poly = eu / SG::cs2 + eu * eu / (2.0 * SG::cs2 * SG::cs2) - usq / (2.0 * SG::cs2);
     const double d = SG::w[j] * (rho_p + (1.0 + rho_p) * poly);
-    store_as(pop + (int64_t)(QF + j) * geo.stride + node, (float)d);
+    store_once(pop + (int64_t)(QF + j) * geo.stride + node, d);
   }
 }
 

@@ -12,7 +12,7 @@ struct LaunchShape {
 };
 
 // The stencil pairs (momentum Q_f x scalar Q_g) with kernel instances: those of the
-// stencil comparisons of Section 4 and of the D3Q7-scalar sweep.  X(qf, qg) is applied
+// stencil comparisons of Sections 3.2-3.3 and of the D3Q7-scalar sweep.  X(qf, qg) is applied
 // to each.
 #define STGV_FOR_EACH_PAIR(X) X(27, 19) X(27, 7) X(19, 7) X(27, 27) X(19, 19) X(19, 15) X(15, 7) X(7, 27)
 

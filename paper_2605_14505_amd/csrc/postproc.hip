@@ -1,5 +1,5 @@
 // Kinetic-energy spectrum: E(k) = sum over the wavevectors with round(|k|) = k of
-// |u_hat|^2 / 2, u_hat = FFT(u / u0) / n^3 (Section 4, spectra at peak activity).
+// |u_hat|^2 / 2, u_hat = FFT(u / u0) / n^3 (Section 3.5, spectra at peak activity).
 // The transforms are rocFFT's; the binning is a grid-stride pass over the
 // half-spectrum of each component into per-block LDS histograms, reduced over
 // the blocks in a fixed order.

@@ -1,5 +1,5 @@
 // Kinetic-energy spectrum of a velocity field on the GPU: three rocFFT real-to-complex
-// transforms and a shell-binning reduction (Section 4, spectra at peak activity).
+// transforms and a shell-binning reduction (Section 3.5, spectra at peak activity).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stddef.h>

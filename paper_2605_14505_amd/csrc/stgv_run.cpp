@@ -9,7 +9,7 @@
 // Allocates the population and work buffers with hipMalloc, queues the initial state
 // and the steps, drains the diagnostic records (printed as CSV: step, t, E_k, E_p,
 // eps_k, eps_p, mass, max|u|) and reports the run's MLUPS from HIP events.  With two
-// or more records it also prints the post-processing of Section 4 over the whole run
+// or more records it also prints the post-processing of Sections 3.4-3.5 over the whole run
 // (bulk flux coefficient, turbulent Froude number, peak buoyancy Reynolds number);
 // --spectrum writes the kinetic-energy spectrum of the final state (k, E(k) per line).
 // --checkpoint writes the final state (header + the FP32 populations of

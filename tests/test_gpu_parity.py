@@ -122,6 +122,26 @@ def test_init_populations_are_the_rounded_oracle_state(q_f, q_g):
     assert np.all(err <= np.abs(ref) * 2.0 ** -23 + 1e-12), err.max()
 
 
+@pytest.mark.parametrize("storage", ["fp16", "bf16"])
+def test_init_reduced_storage_is_rounded_once_from_fp64(storage):
+    # The initial deviations are computed in FP64 and rounded once, to nearest even, into
+    # FP16 / BF16: the same numbers as the oracle's direct FP64 rounding (the two FP64
+    # evaluations of the sines differ by an ulp of a double at most, far below the
+    # distance of any of these values to a rounding boundary of the 11- or 8-bit type).
+    kw = c1_kw()
+    sim = gpu_sim(storage=storage, **kw)
+    pops = sim.populations().cpu().numpy().astype(np.float64)
+    p = oracle_params(kw)
+    f, g = model.init_tgv(p)
+    lf, lg = lat.BY_Q[27], lat.BY_Q[19]
+    ref = np.concatenate([f - lf.w[:, None, None, None], g - lg.w[:, None, None, None]])
+    rounded = model.round_storage(ref, storage)
+    twice = model.round_storage(model.round_storage(ref, "fp32"), storage)
+    print(f"\n{storage}: {int((rounded != twice).sum())} of {rounded.size} values differ between "
+          f"one rounding and rounding through FP32")
+    assert np.array_equal(pops, rounded), int((pops != rounded).sum())
+
+
 # ---------------------------------------------------------------------------
 # the 32^3 Taylor-Green parity case, both forcing schemes
 # ---------------------------------------------------------------------------
