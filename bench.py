@@ -17,10 +17,12 @@ taken on the current kernel sources, the FP64 oracle timed on the host cores
 energy and dissipation histories against the oracle's stored 64^3 histories.
 
 "forms" adds the precision and learned forms: step-kernel throughput of FP16 /
-BF16 weight-shifted storage, of FP64 arithmetic, of every stencil pair and of the
-learned 64^3 step,
-and their energy / dissipation histories (E_k, E_p, eps_k, eps_p, -dE/dt) to
-t = 30 against the plain FP32 256^3 run of the same stratified TGV (Fr 0.6).
+BF16 weight-shifted storage, of FP64 arithmetic, of every stencil pair (FP32, and
+FP16 for the D3Q7-scalar sweep) and of the learned 64^3 step, and their energy /
+dissipation histories (E_k, E_p, eps_k, eps_p, -dE/dt) to t = 30 against the plain
+FP32 256^3 run of the same stratified TGV (Fr 0.6); the 512^3 FP16 case with its
+counter traffic; the 128^3 Fr 0.5 case beside the oracle's 64^3 histories; and the
+256^3 Froude sweep (Fr 0.3, 1, 3: FP16 against FP32 storage, Guo against the shift).
 """
 import argparse
 import json
@@ -31,6 +33,12 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 PEAK_HBM_GBS = 8000.0
+T_START = time.time()
+
+
+def progress(msg):
+    """One progress line on stderr (stdout carries only the JSON result)."""
+    print(f"[bench {time.time() - T_START:6.1f} s] {msg}", file=sys.stderr, flush=True)
 FORCING_NAMES = {"guo": "Guo source-term", "shift": "velocity-shift", "edm": "exact-difference (EDM)",
                  "hcz": "He-Shan-Doolen source-term"}
 
@@ -152,6 +160,67 @@ def history(stgv, kw, t_end, diag_every, packed=None, spectrum_at=None):
     return (recs, spec) if spectrum_at is not None else recs
 
 
+def sweep_128(stgv, stream, steps, warmup):
+    """The 128^3 velocity-shift case at Fr 0.5 (Re 1600, Sc 0.7, FP32) over 5000 steps: MLUPS,
+    and its E_k, E_p, eps_k, eps_p histories beside the FP64 oracle's 64^3 histories of the
+    same flow (tests/golden/series_64_shift.json, 2500 steps: the same physical times), whose
+    difference is the resolution's, not an error of either."""
+    import torch
+    from paper_2605_14505_amd import learned
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "series_64_shift.json")))
+    kw = dict(gold["params"], n=128)
+    ms = kernel_time(stgv, stream, kw, steps, warmup)
+    every = 2 * gold["every"]
+    sim = stgv.Simulation(diag_every=every, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(2 * gold["steps"] + 1)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    recs = sim.diagnostics(raise_unstable=False)
+    sim.close()
+    err = learned.series_errors(recs, gold["fp64"])
+    return {"workload": "128^3 D3Q27x19 velocity shift, Re 1600, Fr 0.5, Sc 0.7, G/N 0.02, FP32, 5001 steps "
+                        f"(t = {recs[-1]['t']:.2f}), records every {every} steps",
+            "kernel_ms": round(ms, 5), "mlups": round(128 ** 3 / (ms * 1e-3) / 1e6, 1),
+            "run_mlups": round(128 ** 3 * (2 * gold["steps"] + 1) / wall / 1e6, 1),
+            "hbm_frac": round(368 * 128 ** 3 / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+            "finite": all(r["nonfinite"] == 0 for r in recs),
+            "vs_oracle_64": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in err.items()
+                             if k in ("records", "ek", "ep", "eps_k", "eps_p", "dEdt")}}
+
+
+def sweep_256_fr(stgv, steps=10000, every=16):
+    """The 256^3 Froude sweep (D3Q27x19, velocity shift, Re 1600, Sc 0.7, G/N 0.02, 10000 steps,
+    t = 12.3): relative L2 errors of the FP16-storage histories against the FP32 run at each
+    Fr, and at Fr 0.3 the Guo source-term run against the velocity shift."""
+    import torch
+    from paper_2605_14505_amd import learned
+    out = {"workload": f"256^3 D3Q27x19, Re 1600, Sc 0.7, G/N 0.02, {steps} steps, records every {every}; "
+                       "relative L2 errors of the histories"}
+    keep = ("finite", "ek", "ep", "eps_k", "eps_p", "dEdt")
+
+    def run(**kw):
+        sim = stgv.Simulation(diag_every=every, n=256, q_f=27, q_g=19, **kw)
+        sim.step(steps + 1)
+        torch.cuda.synchronize()
+        recs = sim.diagnostics(raise_unstable=False)
+        sim.close()
+        return recs
+
+    for fr in (0.3, 1.0, 3.0):
+        phys = learned.physics(fr)
+        ref = run(**phys)
+        e16 = learned.series_errors(run(storage="fp16", **phys), ref)
+        row = {"fp16_vs_fp32": {k: (round(v, 6) if isinstance(v, float) else v) for k, v in e16.items() if k in keep}}
+        if fr == 0.3:
+            eg = learned.series_errors(run(**dict(phys, forcing="guo")), ref)
+            row["guo_vs_shift_fp32"] = {k: (round(v, 6) if isinstance(v, float) else v)
+                                        for k, v in eg.items() if k in keep}
+        out[f"fr_{fr:g}"] = row
+    return out
+
+
 def forms(stgv, stream, t_end, steps, warmup):
     """Precision and learned forms against the plain FP32 256^3 run."""
     import numpy as np
@@ -176,12 +245,27 @@ def forms(stgv, stream, t_end, steps, warmup):
                                "bytes_per_node": bpn,
                                "hbm_frac": round(bpn * n ** 3 / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
     out["stencil_pairs_fp32"] = pairs
+    progress("forms: storage, arithmetic and stencil-pair timings done")
+    # FP16 weight-shifted storage for the pairs of the D3Q7-scalar sweep
+    for qf, qg in ((27, 19), (27, 7), (19, 7)):
+        ms = kernel_time(stgv, stream, dict(base, q_f=qf, q_g=qg, storage="fp16"), steps, warmup)
+        bpn = 2 * (qf + qg) * 2
+        pairs[f"{qf}x{qg}_fp16"] = {"kernel_ms": round(ms, 5), "mlups": round(n ** 3 / (ms * 1e-3) / 1e6, 1),
+                                    "bytes_per_node": bpn,
+                                    "hbm_frac": round(bpn * n ** 3 / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
     # the largest single-GPU case: 512^3, FP16 storage in place (12.35 GB), Re 3200, Fr 0.5
     big = dict(n=512, q_f=27, q_g=19, storage="fp16", **dict(phys, re=3200.0, fr=0.5))
     ms = kernel_time(stgv, stream, big, max(20, steps // 4), warmup)
+    traffic, traffic_src = read_traffic("step_512_27x19_fp16_fp32_shift", 512 ** 3, 184)
     out["large_512_fp16"] = {"kernel_ms": round(ms, 4), "mlups": round(512 ** 3 / (ms * 1e-3) / 1e6, 1),
                              "bytes_per_node": 184,
-                             "hbm_frac": round(184 * 512 ** 3 / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+                             "hbm_frac": round(184 * 512 ** 3 / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                             "traffic": traffic, "traffic_source": traffic_src}
+    progress("forms: 512^3 FP16 timing done")
+    out["sweep_128_fr05"] = sweep_128(stgv, stream, steps, warmup)
+    progress("forms: 128^3 Fr 0.5 run done")
+    out["sweep_256_fr"] = sweep_256_fr(stgv)
+    progress("forms: 256^3 Froude sweep done")
     net_path = os.path.join(ROOT, "paper_2605_14505_amd", "data", "learned64.npz")
     if os.path.exists(net_path):
         z = np.load(net_path, allow_pickle=False)
@@ -194,6 +278,7 @@ def forms(stgv, stream, t_end, steps, warmup):
         ms = kernel_time(stgv, stream, coarse, 20 * steps // 4, warmup, packed)
         rates[name] = {"kernel_ms": round(ms, 5), "mlups": round(nc ** 3 / (ms * 1e-3) / 1e6, 1)}
     out["throughput"] = rates
+    progress("forms: learned-step timing done")
     de_c = max(1, int(round(t_end * learned.steps_per_unit_time(nc) / 100)))
     ref, (spec, spec_ms) = history(stgv, base, t_end, 4 * de_c, spectrum_at=min(15.0, t_end))
     _, _, post = stgv.lbm_postprocess(ref, 1600.0, 0.6, 30.0)
@@ -206,6 +291,7 @@ def forms(stgv, stream, t_end, steps, warmup):
         "spectrum_t": min(15.0, t_end), "spectrum_ms": round(spec_ms, 3),
         "spectrum_slope_k4_24": round(slope, 3),
         "spectrum_head": [float(f"{v:.4e}") for v in spec[:12]]}
+    progress("forms: FP32 256^3 reference history to t = 30 done")
     errs = {}
     for name, extra in (("fp16", {"storage": "fp16"}), ("bf16", {"storage": "bf16"})):
         errs[name] = learned.series_errors(history(stgv, dict(base, **extra), t_end, 4 * de_c), ref)
@@ -214,6 +300,10 @@ def forms(stgv, stream, t_end, steps, warmup):
         errs["learned_64"] = learned.series_errors(
             history(stgv, coarse, t_end, de_c, net.packed if gain > 0 else None), ref)
         errs["learned_64"]["gain"] = gain
+        out["learned_training"] = {
+            "train_fr": [0.3, 1.0, 3.0], "train_seeds": [0], "test_fr": 0.6, "test_seed": 0,
+            "seeds": "seed 0 only: the seed sets only the 1e-6 initial density noise, so further "
+                     "seeds repeat the same teacher flows"}
     keep = ("finite", "ek", "ep", "eps_k", "eps_p", "eps", "dEdt", "dEdt_peak", "dEdt_peak_ref")
     out["errors"] = {k: {q: (round(v[q], 6) if isinstance(v[q], float) else v[q]) for q in keep + ("gain",)
                          if q in v} for k, v in errs.items()}
@@ -275,6 +365,7 @@ def main():
     sim.close()
     del sim
     mlups = n3 * K / wall / 1e6
+    progress(f"timed region: {K} steps, {wall * 1e3 / K:.4f} ms per step")
 
     # ---- the step kernel alone, HIP events on the launch stream
     sim = stgv.Simulation(diag_every=0, **common)
@@ -349,8 +440,10 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_n, args.cpu_sample_steps, args.forcing)
         out["cpu_baseline"]["host_threads_available"] = os.cpu_count()
+        progress("CPU oracle baseline done")
     if not args.no_energy_error:
         out["energy_error"] = energy_error(stgv)
+        progress("energy error against the oracle's 64^3 histories done")
     if not args.no_forms:
         out["forms"] = forms(stgv, stream, args.forms_t, K, W)
     print(json.dumps(out), flush=True)

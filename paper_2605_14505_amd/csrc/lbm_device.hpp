@@ -486,10 +486,14 @@ __device__ __forceinline__ void node_collide(C* f, C* g, const PhysConsts& c,
 // density deviation is hit the same way through the momentum lattice's linear
 // term.  So the step keeps those two quantities exact or nearly so, in FP32:
 //
-// * every momentum population is split as df = hi + lo with hi on the grid of
-//   2^-23 (`grid_split`); sums of grid values below 2 in magnitude are exact in
-//   FP32, so j = sum e df is held as an exact grid part jh plus a small lo sum
-//   whose own rounding is ~2^-24 of 2^-23;
+// * every population is split as df = hi + lo with hi on the grid of 2^-23
+//   (`grid_split`); sums of grid values below 2 in magnitude are exact in FP32,
+//   so drho = sum df, j = sum e df and sum dg are held as an exact grid part plus
+//   a small lo sum whose own rounding is ~2^-24 of 2^-23 (when the split of N^2
+//   puts most of it in the background gradient, rho' reaches 0.1 - 1 and an FP32
+//   rounding of sum dg or of rho' itself is ~1e-8 per node and step);
+// * the stratification source s = -beta u'_z is an exact product pair, and rho'
+//   = sum dg + s/2 a grid part plus a remainder;
 // * the velocities are jh + a small lo part (u' = j/rho = j - j drho/rho:
 //   no rounding of 1 + drho enters it);
 // * the linear equilibrium terms w (drho + 3 e.J) and w (rho' + 3 e.(1 + rho')t)
@@ -500,8 +504,8 @@ __device__ __forceinline__ void node_collide(C* f, C* g, const PhysConsts& c,
 //   without it the sum of the equilibria misses rho' (or drho) by
 //   ~1e-8 (3/2) u^2 at every node and step, always with the same sign, a
 //   steady drift of the scalar and momentum masses.
-// The increment d_i = f^eq_i - f_i is then (hi_i - f_i) + lo_i, whose roundings
-// are at the scale of d rather than of f, and the population is updated once:
+// The increment d_i = f^eq_i - f_i is thus rounded at the scale of d rather than
+// of f, and the population is updated once:
 // f*_i = f_i + (omega d_i + G_i).  The only rounding at the scale of the
 // population is the final one, the one FP32 storage makes anyway.
 // ---------------------------------------------------------------------------
@@ -525,20 +529,21 @@ __device__ __forceinline__ C edot(int ex, int ey, int ez, const C* v) {
   return r;
 }
 
-// Density deviation (plain pair sum) and momentum j = sum e df as grid part
-// (exact) plus remainder.
+// Zeroth moment m0 = sum df and momentum j = sum e df, each as a grid part (an exact
+// sum) plus the sum of the small remainders.
 template <int Q, typename C>
-__device__ __forceinline__ void split_moments(const C* a, C& m0, C* jh, C* jl) {
+__device__ __forceinline__ void split_moments(const C* a, C& m0h, C& m0l, C* jh, C* jl) {
   using S = Stencil<Q>;
-  C s = a[0];
+  grid_split(a[0], m0h, m0l);
 #pragma unroll
   for (int k = 0; k < 3; ++k) { jh[k] = C(-0.0); jl[k] = C(-0.0); }
 #pragma unroll
   for (int i = 1; i < Q; i += 2) {
-    s += a[i] + a[i + 1];
     C h0, l0, h1, l1;
     grid_split(a[i], h0, l0);
     grid_split(a[i + 1], h1, l1);
+    m0h += h0 + h1;
+    m0l += l0 + l1;
     const C dh = h0 - h1, dl = l0 - l1;    // e_{i+1} = -e_i
     const int e[3] = {S::ex[i], S::ey[i], S::ez[i]};
 #pragma unroll
@@ -548,12 +553,27 @@ __device__ __forceinline__ void split_moments(const C* a, C& m0, C* jh, C* jl) {
       jl[k] += e[k] > 0 ? dl : -dl;
     }
   }
-  m0 = s;
+}
+
+// Zeroth moment only, as grid part plus remainder.
+template <int Q, typename C>
+__device__ __forceinline__ void split_sum(const C* a, C& mh, C& ml) {
+  grid_split(a[0], mh, ml);
+#pragma unroll
+  for (int i = 1; i < Q; i += 2) {
+    C h0, l0, h1, l1;
+    grid_split(a[i], h0, l0);
+    grid_split(a[i + 1], h1, l1);
+    mh += h0 + h1;
+    ml += l0 + l1;
+  }
 }
 
 template <typename C>
 struct StepMacro {
-  C drho, rho, inv, dsig, rho_p, s, Fz;
+  C drho, rho, inv, dsig, rho_p, s, Fz;   // FP32 values
+  C dr_h, dr_l;  // drho = dr_h + dr_l: grid part (exact sum) and remainder
+  C rp_h, rp_l;  // rho' likewise (sum g - 1 + s/2 with s as an exact product pair)
   C jh[3];      // grid part of j = sum e df, shared by every velocity below
   C j[3];       // j (FP32 value), for the diagnostics
   C jeq_l[3];   // rho v_eq - jh: the equilibrium momentum's remainder (j + k F e_z)
@@ -564,21 +584,43 @@ struct StepMacro {
   C fl[3];      // (1 + rho') t - jh: remainder of the scalar equilibrium's flux
 };
 
-template <int QF, int QG, int FORCE, typename C>
+// EXACT: the moment sums in split form (FP32 storage).  With 2-byte storage the store
+// rounds each deviation at 2^-11 (FP16) or 2^-8 (BF16) of itself, far above anything the
+// exact sums save, so those steps take plain pair sums (the remainders are then zero)
+// and keep only the cheap error-free parts (the fused increments, the source pair).
+template <int QF, int QG, int FORCE, bool EXACT, typename C>
 __device__ __forceinline__ void step_macro(const C* f, const C* g, const PhysConsts& c,
                                            StepMacro<C>& m) {
   C jl[3];
-  split_moments<QF>(f, m.drho, m.jh, jl);
-  m.dsig = pair_sum<QG>(g);
+  C sg_h, sg_l;
+  if constexpr (EXACT) {
+    split_moments<QF>(f, m.dr_h, m.dr_l, m.jh, jl);
+    split_sum<QG>(g, sg_h, sg_l);
+  } else {
+    pair_moments<QF>(f, m.dr_h, m.jh[0], m.jh[1], m.jh[2]);
+    m.dr_l = C(0);
+    jl[0] = jl[1] = jl[2] = C(0);
+    sg_h = pair_sum<QG>(g);
+    sg_l = C(0);
+  }
+  m.drho = m.dr_h + m.dr_l;
+  m.dsig = sg_h + sg_l;
   m.rho = C(1) + m.drho;                          // Eq. (6)
   m.inv = C(1) / m.rho;
   const C q = m.drho * m.inv;                     // u' = j / rho = j - j drho / rho
   C upl[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) upl[k] = jl[k] - (m.jh[k] + jl[k]) * q;
-  const C upz = m.jh[2] + upl[2];
-  m.s = -upz * (C)c.beta;                         // Eqs. (12)-(13), bare u_z
-  m.rho_p = m.dsig + C(0.5) * m.s;                // Eqs. (16)-(17)
+  // Eqs. (12)-(13), bare u_z: s = -beta u'_z = s_h + s_l, s_h = fl(-beta jh_z) and the
+  // product's exact residual carried in s_l
+  const C beta = (C)c.beta;
+  const C s_h = -beta * m.jh[2];
+  const C s_l = fma_c(-beta, upl[2], fma_c(-beta, m.jh[2], -s_h));
+  m.s = s_h + s_l;
+  // Eqs. (16)-(17): rho' = sum g - 1 + s/2, grid part exact
+  m.rp_h = sg_h;
+  m.rp_l = fma_c(C(0.5), s_h, fma_c(C(0.5), s_l, sg_l));
+  m.rho_p = m.rp_h + m.rp_l;
   m.Fz = -(C)c.G * m.rho_p;                       // Eq. (18)
   const C fz_inv = m.Fz * m.inv;
   m.ul[0] = upl[0];
@@ -608,17 +650,35 @@ __device__ __forceinline__ void step_macro(const C* f, const C* g, const PhysCon
   }
 }
 
+// The relaxation increment w (y + rq) - p of one population p, y the exact grid part.
+// EXACT: w y = ph + pe exactly (the fused multiply-add residual), ph - p exact, and the
+// remainders, the residual and the weight's FP32 residual on all of it summed at the
+// increment's scale, so the only rounding of that size is the last one.  (A chain of
+// three fused multiply-adds, fma(wl, y + rq, fma(w, rq, fma(w, y, -p))), rounds three
+// times at that size and measurably loses accuracy at tau ~ 1/2.)  Otherwise the chain,
+// for 2-byte storage whose store rounding is far larger.
+template <bool EXACT, typename C>
+__device__ __forceinline__ C increment(C w, C wl, C y, C rq, C p) {
+  if constexpr (EXACT) {
+    const C ph = w * y;
+    C pe = fma_c(w, y, -ph);
+    pe = fma_c(wl, y + rq, pe);
+    return (ph - p) + fma_c(w, rq, pe);
+  } else {
+    return fma_c(wl, y + rq, fma_c(w, rq, fma_c(w, y, -p)));
+  }
+}
+
 // Post-collision populations of both lattices, in place (Eqs. (5), (8)-(11),
 // (14)-(15) with the forcing scheme's term).
-template <int QF, int QG, int FORCE, typename C>
+template <int QF, int QG, int FORCE, bool EXACT, typename C>
 __device__ __forceinline__ void step_collide(C* f, C* g, const PhysConsts& c, const StepMacro<C>& m) {
   using SF = Stencil<QF>;
   using SG = Stencil<QG>;
   constexpr C icf = C(1.0 / SF::cs2);
   constexpr C icg = C(1.0 / SG::cs2);
   const C omega_f = (C)c.omega_f, omega_g = (C)c.omega_g;
-  C dr_h, dr_l;
-  grid_split(m.drho, dr_h, dr_l);
+  const C dr_h = m.dr_h, dr_l = m.dr_l;
   const C vsq = m.v[0] * m.v[0] + m.v[1] * m.v[1] + m.v[2] * m.v[2];
   const C qb_f = -C(0.5) * icf * vsq;
   const C half_c = (C(1) - C(0.5) * omega_f) * m.Fz;
@@ -641,11 +701,7 @@ __device__ __forceinline__ void step_collide(C* f, C* g, const PhysConsts& c, co
       const C y = fma_c(C(sgn) * icf, ejh, dr_h);          // drho + 3 e.J, grid parts: exact
       const C r = fma_c(C(sgn) * icf, ejl, dr_l);          // remainders
       const C rq = r + qv;
-      const C ph = w * y;
-      C pe = fma_c(w, y, -ph);                              // w y = ph + pe exactly
-      pe = fma_c(wl, y + rq, pe);                           // the weight's residual on all of it
-      const C lo = fma_c(w, rq, pe);
-      const C d = (ph - f[k]) + lo;                         // f^eq - f
+      const C d = increment<EXACT>(w, wl, y, rq, f[k]);    // f^eq - f
       C force = C(0);
       if (FORCE == FORCE_GUO || FORCE == FORCE_EDM) {
         //   Guo: G_i = (1 - omega/2) w [(e_z - u_z) / c^2 + (e.u) e_z / c^4] Fz;
@@ -661,14 +717,13 @@ __device__ __forceinline__ void step_collide(C* f, C* g, const PhysConsts& c, co
         force = w * bracket_c * br;
       } else if (FORCE == FORCE_HCZ) {
         //   HCZ: G_i = (1 - omega/2) (e_z - u_z) Fz / (rho c^2) f^eq_i(u)
-        force = hcz_c * (C(sgn * ez) - m.u[2]) * (w + (ph + lo));
+        force = hcz_c * (C(sgn * ez) - m.u[2]) * fma_c(w, y + rq, w);
       }
       f[k] = f[k] + fma_c(omega_f, d, force);
     }
   }
   // scalar lattice: g^eq_j = w [rho' + 3 e.(1 + rho') t + (1 + rho')(xi^2/2 - t^2/(2c^2))]
-  C rp_h, rp_l;
-  grid_split(m.rho_p, rp_h, rp_l);
+  const C rp_h = m.rp_h, rp_l = m.rp_l;
   const C conc = C(1) + m.rho_p;
   const C tsq = (FORCE == FORCE_EDM) ? m.t[0] * m.t[0] + m.t[1] * m.t[1] + m.t[2] * m.t[2] : vsq;
   const C qb_g = -C(0.5) * icg * tsq;
@@ -689,11 +744,7 @@ __device__ __forceinline__ void step_collide(C* f, C* g, const PhysConsts& c, co
       const C y = fma_c(C(sgn) * icg, ejh, rp_h);
       const C r = fma_c(C(sgn) * icg, ejl, rp_l);
       const C rq = r + qv;
-      const C ph = w * y;
-      C pe = fma_c(w, y, -ph);
-      pe = fma_c(wl, y + rq, pe);
-      const C lo = fma_c(w, rq, pe);
-      const C h = (ph - g[k]) + lo;                         // g^eq - g
+      const C h = increment<EXACT>(w, wl, y, rq, g[k]);    // g^eq - g
       g[k] = g[k] + fma_c(omega_g, h, ws);
     }
   }

@@ -44,14 +44,14 @@ __global__ STGV_STEP_BOUNDS void lbm_step_kernel(T* pop, T* dst, Geometry geo,
     gather<QF, T, MODE>(f, pop, 0, ix, geo.stride);
     gather<QG, T, MODE>(g, pop, QF, ix, geo.stride);
     StepMacro<C> m;
-    step_macro<QF, QG, FORCE>(f, g, c, m);
+    step_macro<QF, QG, FORCE, sizeof(T) == 4>(f, g, c, m);
     if (FLAGS & (K_FIELDS | K_PARTIALS)) {
       const NodeMacro<C> dm = diag_macro(m);
       if (FLAGS & K_FIELDS) write_fields(dm, fields, ix.base, (int64_t)n * n * n);
       if (kPart) node_partials(dm, c, acc);
     }
     if (FLAGS & K_COLLIDE) {
-      step_collide<QF, QG, FORCE>(f, g, c, m);
+      step_collide<QF, QG, FORCE, sizeof(T) == 4>(f, g, c, m);
       scatter<QF, T, MODE>(f, dst, 0, ix, geo.stride);
       scatter<QG, T, MODE>(g, dst, QF, ix, geo.stride);
     }
@@ -77,8 +77,8 @@ __global__ STGV_STEP_BOUNDS void lbm_step_xstaged_kernel(T* pop, Geometry geo, P
   gather<QF, T, MODE_ODD>(f, pop, 0, ix, geo.stride);
   gather<QG, T, MODE_ODD>(g, pop, QF, ix, geo.stride);
   StepMacro<C> m;
-  step_macro<QF, QG, FORCE>(f, g, c, m);
-  step_collide<QF, QG, FORCE>(f, g, c, m);
+  step_macro<QF, QG, FORCE, sizeof(T) == 4>(f, g, c, m);
+  step_collide<QF, QG, FORCE, sizeof(T) == 4>(f, g, c, m);
   const XLane l = make_xlane();
   stage_x<QF>(f, xs, 0, l);
   stage_x<QG>(g, xs, KF, l);

@@ -88,13 +88,32 @@ int write_spectrum(lbm_ctx* ctx, int n, const char* path) {
 }
 
 // Checkpoint file: this header, then (q_f + q_g) n^3 FP32 population deviations in the
-// order of lbm_read_populations.
+// order of lbm_read_populations.  The header keeps the run's whole parameter set, so a
+// resume with another box, stencil pair, forcing, storage, arithmetic, layout or physics
+// is refused (the diagnostic cadence and the array padding may change).
 struct CkptHeader {
-  char magic[8];       // "STGVCKP1"
-  int32_t n, q_f, q_g, storage;
+  char magic[8];       // "STGVCKP2"
+  lbm_params params;
   int64_t step;
 };
-constexpr char kMagic[8] = {'S', 'T', 'G', 'V', 'C', 'K', 'P', '1'};
+constexpr char kMagic[8] = {'S', 'T', 'G', 'V', 'C', 'K', 'P', '2'};
+
+// The first parameter in which a checkpoint's run differs from this one, or nullptr.
+const char* params_mismatch(const lbm_params& a, const lbm_params& b) {
+  if (a.n != b.n) return "box size";
+  if (a.q_f != b.q_f || a.q_g != b.q_g) return "stencil pair";
+  if (a.forcing != b.forcing) return "forcing";
+  if (a.storage != b.storage) return "storage";
+  if (a.compute != b.compute) return "arithmetic";
+  if (a.layout != b.layout) return "layout";
+  if (a.u0 != b.u0) return "u0";
+  if (a.re != b.re) return "Re";
+  if (a.fr != b.fr) return "Fr";
+  if (a.sc != b.sc) return "Sc";
+  if (a.g_over_n != b.g_over_n) return "G/N";
+  if (a.noise_amp != b.noise_amp || a.seed != b.seed) return "initial noise";
+  return nullptr;
+}
 
 int save_state(lbm_ctx* ctx, const lbm_params& p, const char* path) {
   const size_t count = (size_t)(p.q_f + p.q_g) * p.n * p.n * p.n;
@@ -114,7 +133,7 @@ int save_state(lbm_ctx* ctx, const lbm_params& p, const char* path) {
   } else {
     CkptHeader hd{};
     std::memcpy(hd.magic, kMagic, sizeof(kMagic));
-    hd.n = p.n; hd.q_f = p.q_f; hd.q_g = p.q_g; hd.storage = p.storage;
+    hd.params = p;
     hd.step = lbm_get_step(ctx);
     FILE* f = std::fopen(path, "wb");
     if (!f || std::fwrite(&hd, sizeof(hd), 1, f) != 1 || std::fwrite(host.data(), sizeof(float), count, f) != count) {
@@ -135,12 +154,16 @@ int read_checkpoint(const lbm_params& p, const char* path, std::vector<float>& h
   CkptHeader hd{};
   const size_t count = (size_t)(p.q_f + p.q_g) * p.n * p.n * p.n;
   host.resize(count);
-  const bool ok = std::fread(&hd, sizeof(hd), 1, f) == 1 && std::memcmp(hd.magic, kMagic, sizeof(kMagic)) == 0 &&
-                  hd.n == p.n && hd.q_f == p.q_f && hd.q_g == p.q_g && hd.step >= 0 &&
-                  std::fread(host.data(), sizeof(float), count, f) == count;
+  const bool head = std::fread(&hd, sizeof(hd), 1, f) == 1 && std::memcmp(hd.magic, kMagic, sizeof(kMagic)) == 0 &&
+                   hd.step >= 0;
+  const char* differs = head ? params_mismatch(hd.params, p) : nullptr;
+  const bool ok = head && !differs && std::fread(host.data(), sizeof(float), count, f) == count;
   std::fclose(f);
   if (!ok) {
-    std::fprintf(stderr, "stgv_run: %s is not a checkpoint of a %d^3 D3Q%dxD3Q%d run\n", path, p.n, p.q_f, p.q_g);
+    if (differs)
+      std::fprintf(stderr, "stgv_run: %s is a checkpoint of another run (its %s differs)\n", path, differs);
+    else
+      std::fprintf(stderr, "stgv_run: %s is not a checkpoint of a %d^3 D3Q%dxD3Q%d run\n", path, p.n, p.q_f, p.q_g);
     return 2;
   }
   step = hd.step;

@@ -23,9 +23,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PROFILES = os.path.join(ROOT, "profiles")
 
 
-# the sources the FP32 step kernel is compiled from (the profiled kernel)
+# the sources the step kernels are compiled from (the profiled kernels)
 STEP_SOURCES = ("stencil.hpp", "lbm_device.hpp", "mlp_device.hpp", "lbm_kernels.hpp", "lbm_launch.hpp",
-                "lbm_instances.hpp", "lbm_fp32.hip")
+                "lbm_instances.hpp", "lbm_fp32.hip", "lbm_fp16.hip", "lbm_bf16.hip", "learned_step.hip")
 
 
 def kernel_source_hash():
@@ -53,12 +53,31 @@ def kernel_stats(trace_dir):
     return out
 
 
-def counter_means(pmc_dir):
+def counter_table(pmc_dir):
+    """{kernel: {counter: mean value per dispatch}} of one rocprofv3 --pmc run."""
     rows = list(csv.DictReader(open(_one(os.path.join(pmc_dir, "*counter_collection.csv")))))
     agg = {}
     for r in rows:
-        agg.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
-    return {k: sum(v) / len(v) for k, v in agg.items()}
+        agg.setdefault(r["Kernel_Name"], {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    return {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in agg.items()}
+
+
+def counter_means(pmc_dir):
+    """{kernel: mean value per dispatch} of a run that collected one counter."""
+    return {k: next(iter(cs.values())) for k, cs in counter_table(pmc_dir).items()}
+
+
+def is_step_kernel(name):
+    return "lbm_step_kernel" in name or "lbm_step_xstaged_kernel" in name
+
+
+def is_plain_step(name):
+    """A time step without diagnostic outputs: FLAGS == 1 (the last template argument, in
+    the demangled or the mangled name), or the LDS-staged odd step, which has no flags."""
+    if "lbm_step_xstaged_kernel" in name:
+        return True
+    m = re.search(r"lbm_step_kernel<[^>]*, (\d+)>\(", name) or re.search(r"lbm_step_kernelI.*ELi(\d+)EEEv", name)
+    return bool(m) and m.group(1) == "1"
 
 
 def main():
@@ -72,6 +91,10 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--bytes-per-node", type=int, default=368)
     ap.add_argument("--note", default="")
+    ap.add_argument("--pmc", action="append", default=[],
+                    help="further --pmc folders of the same command: their counters per kernel "
+                         "go to profiles/KEY_pmc.txt")
+    ap.add_argument("--match", default="", help="only kernels whose name contains this in KEY_pmc.txt")
     a = ap.parse_args()
     os.makedirs(PROFILES, exist_ok=True)
     if a.trace:
@@ -90,7 +113,7 @@ def main():
         copy = [k for k in fetch if "bw_copy_kernel" in k][0]
         kib = a.copy_bytes / 1024.0
         f_scale, w_scale = kib / fetch[copy], kib / write[copy]
-        steps = [k for k in fetch if "lbm_step_kernel" in k and k in write]
+        steps = [k for k in fetch if is_step_kernel(k) and k in write]
         n3 = a.n ** 3
         path = os.path.join(PROFILES, f"{a.key}_counters.txt")
         with open(path, "w") as fh:
@@ -106,17 +129,31 @@ def main():
                 fb, wb = fetch[k] * f_scale * 1024, write[k] * w_scale * 1024
                 fh.write(f"# {k[:110]}\n#   fetch {fb / 1e9:.4f} GB  write {wb / 1e9:.4f} GB  "
                          f"total/algorithmic {(fb + wb) / algo:.4f}\n")
-                # plain steps (no diagnostic outputs): FLAGS == 1, the last template
-                # argument, in the demangled or the mangled name
-                m = re.search(r"lbm_step_kernel<[^>]*, (\d+)>\(", k) or \
-                    re.search(r"lbm_step_kernelI.*ELi(\d+)EEEv", k)
-                if m and m.group(1) == "1":
+                if is_plain_step(k):
                     plain.append(fb + wb)
             per_launch = sum(plain) / len(plain) if plain else float("nan")
             fh.write(f"source_hash = {kernel_source_hash()}\n")
             fh.write(f"algorithmic_bytes_per_launch = {algo}\n")
             fh.write(f"hbm_bytes_per_launch = {per_launch:.0f}\n")
             fh.write(f"fetch_scale = {f_scale:.5f}\nwrite_scale = {w_scale:.5f}\n")
+        print("wrote", path)
+    if a.pmc:
+        table = {}
+        for d in a.pmc:
+            for k, cs in counter_table(d).items():
+                table.setdefault(k, {}).update(cs)
+        path = os.path.join(PROFILES, f"{a.key}_pmc.txt")
+        with open(path, "w") as fh:
+            fh.write("# rocprofv3 --pmc counters, mean per dispatch (one run per counter set)\n")
+            fh.write(f"# command: {a.cmd}\n# kernel sources: {kernel_source_hash()}\n")
+            if a.note:
+                fh.write(f"# {a.note}\n")
+            for k in sorted(table):
+                if a.match and a.match not in k:
+                    continue
+                fh.write(f"{k[:150]}\n")
+                for c in sorted(table[k]):
+                    fh.write(f"  {c} = {table[k][c]:.6g}\n")
         print("wrote", path)
 
 

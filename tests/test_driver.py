@@ -84,24 +84,43 @@ def test_driver_records_match_the_binding(forcing, storage, tmp_path):
         assert abs(float(e) - ref) <= 1e-7 * total, k
 
 
-def _header(n, q_f=27, q_g=19, storage=0, step=0):
+def _header(n, q_f=27, q_g=19, storage=0, step=0, fr=1.0, forcing=1):
+    # the lbm_params of include/stgv.h, as the driver's defaults set them, then the step
     import struct
-    return b"STGVCKP1" + struct.pack("<iiiiq", n, q_f, q_g, storage, step)
+    params = struct.pack("<10i6dQ", n, q_f, q_g, forcing, storage, 0, 0, 50, -1, 0,
+                         0.05, 1600.0, fr, 0.7, 0.02, 1e-6, 0)
+    return b"STGVCKP2" + params + struct.pack("<q", step)
 
 
-@pytest.mark.parametrize("content", [None, b"junk", "wrong_n", "truncated"])
+@pytest.mark.parametrize("content", [None, b"junk", "wrong_n", "truncated", "wrong_storage", "wrong_fr",
+                                     "wrong_forcing", "old_format"])
 def test_resume_rejects_what_is_not_a_checkpoint_of_the_run(content, tmp_path):
     # the file is read and checked before any GPU work: exit status 2
     path = tmp_path / "state.bin"
+    body = bytes(46 * 32 ** 3 * 4)
     if content == "wrong_n":
         path.write_bytes(_header(16) + bytes(46 * 16 ** 3 * 4))
     elif content == "truncated":
         path.write_bytes(_header(32) + bytes(100))
+    elif content == "wrong_storage":
+        path.write_bytes(_header(32, storage=1) + body)
+    elif content == "wrong_fr":
+        path.write_bytes(_header(32, fr=0.5) + body)
+    elif content == "wrong_forcing":
+        path.write_bytes(_header(32, forcing=0) + body)
+    elif content == "old_format":
+        import struct
+        path.write_bytes(b"STGVCKP1" + struct.pack("<iiiiq", 32, 27, 19, 0, 0) + body)
     elif content is not None:
         path.write_bytes(content)
     r = run("--n", 32, "--resume", path)
     assert r.returncode == 2
     assert str(path) in r.stderr
+    if content in ("wrong_storage", "wrong_fr", "wrong_forcing"):
+        assert {"wrong_storage": "storage", "wrong_fr": "Fr", "wrong_forcing": "forcing"}[content] in r.stderr
+    # the header that matches is accepted up to the body (a full one is the GPU test's)
+    if content == "truncated":
+        assert "not a checkpoint" in r.stderr
 
 
 @pytest.mark.gpu

@@ -139,18 +139,27 @@ def test_init_reduced_storage_is_rounded_once_from_fp64(storage):
     twice = model.round_storage(model.round_storage(ref, "fp32"), storage)
     print(f"\n{storage}: {int((rounded != twice).sum())} of {rounded.size} values differ between "
           f"one rounding and rounding through FP32")
-    assert np.array_equal(pops, rounded), int((pops != rounded).sum())
+    # The oracle holds full populations (f ~ w), so a deviation below ~1e-16 w cancels to 0
+    # there (6480 such values here, nodes where p0 and the velocity vanish to rounding), while
+    # the kernel forms the deviation directly; BF16 keeps FP32's exponent range and can hold
+    # it.  Bit equality holds above the oracle's own FP64 resolution.
+    big = np.abs(ref) > 1e-14
+    assert np.array_equal(pops[big], rounded[big]), int((pops[big] != rounded[big]).sum())
+    assert np.all(np.abs(pops[~big] - rounded[~big]) <= 1e-14)
 
 
 # ---------------------------------------------------------------------------
 # the 32^3 Taylor-Green parity case, both forcing schemes
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("g_over_n", [1.0, 0.02])
 @pytest.mark.parametrize("compute", ["fp32", "fp64"])
 @pytest.mark.parametrize("forcing", ["guo", "shift", "edm", "hcz"])
-def test_tgv_parity_32(forcing, compute):
-    """The 32^3 case after 100 and 200 steps.  With FP64 arithmetic every field is within
-    the stated 1e-5 relative L-infinity of the FP64 oracle after 100 steps."""
-    kw = c1_kw(forcing=forcing)
+def test_tgv_parity_32(forcing, compute, g_over_n):
+    """The 32^3 case after 100 and 200 steps: every field within the stated 1e-5 relative
+    L-infinity of the FP64 oracle, FP32 and FP64 arithmetic alike.  G/N = 1 is the reading
+    of the unsplit N^2; G/N = 0.02 is the split every long run uses (rho' 50x larger for
+    the same buoyancy)."""
+    kw = c1_kw(forcing=forcing, g_over_n=g_over_n)
     ref = oracle_fields_series(tuple(sorted(kw.items())), (100, 200))
     sim = gpu_sim(compute=compute, **kw)
     sim.step(100)
@@ -158,8 +167,8 @@ def test_tgv_parity_32(forcing, compute):
     sim.step(100)
     e200 = field_errors(sim.fields().cpu().numpy(), ref[200])
     f100, f200 = storage_floor(kw, 100, "fp32"), storage_floor(kw, 200, "fp32")
-    print(f"\n{forcing} {compute}: 100 steps {e100}\n  fp32-storage floor {f100}"
-          f"\n{forcing} {compute}: 200 steps {e200}\n  fp32-storage floor {f200}")
+    print(f"\n{forcing} {compute} G/N {g_over_n}: 100 steps {e100}\n  fp32-storage floor {f100}"
+          f"\n{forcing} {compute} G/N {g_over_n}: 200 steps {e200}\n  fp32-storage floor {f200}")
     for k in FIELDS:
         assert e100[k] <= BAR and e200[k] <= BAR, (k, e100[k], e200[k])
         assert e100[k] <= K_FLOOR * f100[k] + 1e-7, (k, e100[k], f100[k])

@@ -13,7 +13,7 @@ import pytest
 
 from oracle import lattice as lat, micro, model
 
-# the pairs of the paper's stencil comparisons (Section 4) and of the benchmark sweep
+# the pairs of the paper's stencil comparisons (Sections 3.2-3.3) and of the benchmark sweep
 PAIRS = [(27, 19), (27, 7), (19, 7), (27, 27), (19, 19), (19, 15), (15, 7), (7, 27)]
 
 
