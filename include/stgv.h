@@ -209,6 +209,19 @@ int lbm_mlp_grad(const void* packed_dev, const float* x_dev, const float* y_dev,
                  const int64_t* idx_dev, int64_t batch, float* grad_dev, double* loss_dev,
                  void* work_dev, size_t work_bytes, void* hip_stream);
 
+/* lbm_mlp_grad for callers that cannot allocate (code under HIP graph capture, tight
+ * training loops, hosts that forbid hipMalloc): the same kernels and the same result,
+ * bit for bit, with the per-block partial sums in a device array built into the
+ * library (about 10 MB per GPU, held until the process ends) instead of a workspace.
+ * batch <= LBM_MLP_STATIC_MAX_BATCH, else LBM_ESIZE before any device work.  Runs on
+ * the current device (the one hip_stream and the buffers belong to); allocates
+ * nothing.  Calls that overlap on one GPU (other streams or host threads) share the
+ * array and race: serialise them. */
+#define LBM_MLP_STATIC_MAX_BATCH 16384
+int lbm_mlp_grad_static(const void* packed_dev, const float* x_dev, const float* y_dev,
+                        const int64_t* idx_dev, int64_t batch, float* grad_dev, double* loss_dev,
+                        void* hip_stream);
+
 /* One Adam step (Kingma & Ba; beta1 0.9, beta2 0.999, eps 1e-8) at step t >= 1 on
  * params / m / v (FP32, LBM_MLP_PARAMS each). */
 int lbm_mlp_adam(float* params_dev, float* m_dev, float* v_dev, const float* grad_dev, int64_t t,

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "../../include/stgv.h"
@@ -784,6 +785,63 @@ int lbm_mlp_grad(const void* packed, const float* x, const float* y, const int64
   const int64_t blocks = (batch + 63) / 64;
   float* gpart = (float*)work;
   double* lpart = (double*)((char*)work + align_up((size_t)blocks * mlp::N_PARAMS * sizeof(float), kAlign));
+  hipError_t e = mlp_launch_grad(packed, x, y, idx, batch, gpart, lpart, grad, loss, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "gradient kernels");
+  return LBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The gradient without a caller workspace: its per-block partial sums live in a
+// file-scope device array of fixed size, one copy per GPU for the whole process.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int64_t kStaticGradBlocks = (LBM_MLP_STATIC_MAX_BATCH + 63) / 64;
+constexpr size_t kStaticGpartBytes = ((size_t)kStaticGradBlocks * mlp::N_PARAMS * sizeof(float) + 255) / 256 * 256;
+constexpr size_t kStaticScratchBytes = kStaticGpartBytes + (size_t)kStaticGradBlocks * sizeof(double);
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+// The partial gradients (kStaticGradBlocks x LBM_MLP_PARAMS FP32) and losses (FP64)
+// of lbm_mlp_grad_static.  Host code never uses this name as an address: it takes the
+// device address that hipGetSymbolAddress returns for the current GPU (scratch_address).
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+// Device address of `scratch` on the current GPU, looked up once per device (with that
+// device current) and kept.
+static int scratch_address(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) { set_err(g_err, "device %d beyond the library's %d", dev, kMaxDevices); return LBM_EINVAL; }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetSymbolAddress of the gradient scratch");
+    if (!ptr) { set_err(g_err, "hipGetSymbolAddress returned no address for the gradient scratch"); return LBM_EHIP; }
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return LBM_OK;
+}
+
+int lbm_mlp_grad_static(const void* packed, const float* x, const float* y, const int64_t* idx,
+                        int64_t batch, float* grad, double* loss, void* stream) {
+  if (!packed || !x || !y || !idx || !grad || batch <= 0) { set_err(g_err, "invalid argument"); return LBM_EINVAL; }
+  if (batch > LBM_MLP_STATIC_MAX_BATCH) {
+    set_err(g_err, "batch of %lld rows exceeds the %d rows of the built-in gradient scratch",
+            (long long)batch, (int)LBM_MLP_STATIC_MAX_BATCH);
+    return LBM_ESIZE;
+  }
+  void* base = nullptr;
+  const int st = scratch_address(&base);
+  if (st != LBM_OK) return st;
+  // every block writes all of its partials before the reduction reads them, so nothing
+  // left by an earlier call needs clearing
+  float* gpart = static_cast<float*>(base);
+  double* lpart = reinterpret_cast<double*>(static_cast<char*>(base) + kStaticGpartBytes);
   hipError_t e = mlp_launch_grad(packed, x, y, idx, batch, gpart, lpart, grad, loss, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(nullptr, e, "gradient kernels");
   return LBM_OK;

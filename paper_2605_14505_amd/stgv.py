@@ -86,6 +86,7 @@ def _load():
         "lbm_mlp_forward": (ctypes.c_int, [vp, vp, i64, vp, vp]),
         "lbm_mlp_grad_work_bytes": (sz, [i64]),
         "lbm_mlp_grad": (ctypes.c_int, [vp, vp, vp, vp, i64, vp, vp, vp, sz, vp]),
+        "lbm_mlp_grad_static": (ctypes.c_int, [vp, vp, vp, vp, i64, vp, vp, vp]),
         "lbm_mlp_adam": (ctypes.c_int, [vp, vp, vp, vp, i64, dbl, vp]),
         "lbm_mlp_norm_work_bytes": (sz, []),
         "lbm_mlp_norm": (ctypes.c_int, [vp, vp, i64, vp, vp, sz, vp]),
@@ -112,7 +113,7 @@ EXPORTED = ("lbm_query_sizes", "lbm_derived", "lbm_init_tgv", "lbm_step", "lbm_s
             "lbm_diagnostics", "lbm_read_fields", "lbm_read_populations", "lbm_load_populations",
             "lbm_stencil_info", "lbm_bw_probe", "lbm_get_step", "lbm_last_error",
             "lbm_status_string", "lbm_destroy", "lbm_mlp_packed_bytes", "lbm_mlp_pack",
-            "lbm_mlp_forward", "lbm_mlp_grad_work_bytes", "lbm_mlp_grad", "lbm_mlp_adam",
+            "lbm_mlp_forward", "lbm_mlp_grad_work_bytes", "lbm_mlp_grad", "lbm_mlp_grad_static", "lbm_mlp_adam",
             "lbm_mlp_norm_work_bytes", "lbm_mlp_norm", "lbm_restrict", "lbm_training_pairs",
             "lbm_set_mlp", "lbm_postprocess", "lbm_spectrum_shells", "lbm_spectrum_work_bytes",
             "lbm_ke_spectrum")
@@ -228,6 +229,14 @@ def lbm_mlp_grad_work_bytes(batch):
 def lbm_mlp_grad(packed, x, y, idx, batch, grad, loss, work, stream):
     _check(LIB.lbm_mlp_grad(_ptr(packed), _ptr(x), _ptr(y), _ptr(idx), batch, _ptr(grad), _ptr(loss),
                             _ptr(work), work.numel() * work.element_size(), ctypes.c_void_p(stream)))
+
+
+LBM_MLP_STATIC_MAX_BATCH = 16384     # include/stgv.h
+
+
+def lbm_mlp_grad_static(packed, x, y, idx, batch, grad, loss, stream):
+    _check(LIB.lbm_mlp_grad_static(_ptr(packed), _ptr(x), _ptr(y), _ptr(idx), batch, _ptr(grad), _ptr(loss),
+                                   ctypes.c_void_p(stream)))
 
 
 def lbm_mlp_adam(params, m, v, grad, t, lr, stream):
