@@ -22,14 +22,40 @@ namespace stgv {
 #define STGV_STEP_BOUNDS __launch_bounds__(256)
 #endif
 
+// Block coordinates of a node kernel.  The hardware hands consecutive workgroups to the
+// 8 XCDs in turn, each with its own L2, so the blocks that split one row along x sit on
+// different XCDs; the steps whose loads or stores are shifted along x (odd AA, A-B) share
+// a line at every block seam, and then fetch it from HBM twice (at 512^3 FP16, 15 % more
+// than the algorithmic bytes).  For those steps, when rows are split, the workgroups are
+// renumbered so that the blocks of one row group are 8 apart in dispatch order, i.e. on
+// one XCD: workgroup L = 8 (nbx q + h) + k holds x-block h of row group 8 q + k.  A
+// bijection whenever the row groups (gridDim.y gridDim.z) are a multiple of 8.
+struct BlockXYZ { int bx, by, bz; };
+
+template <int MODE>
+__device__ __forceinline__ BlockXYZ node_block() {
+  BlockXYZ b{(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z};
+  const int gx = (int)gridDim.x, gy = (int)gridDim.y;
+  if (MODE != MODE_EVEN && gx > 1 && ((gy * (int)gridDim.z) & 7) == 0) {
+    const int L = b.bx + gx * (b.by + gy * b.bz);
+    const int k = L & 7, rest = L >> 3;
+    const int rg = (rest / gx) * 8 + k;
+    b.bx = rest % gx;
+    b.by = rg % gy;
+    b.bz = rg / gy;
+  }
+  return b;
+}
+
 template <int QF, int QG, int FORCE, typename T, typename C, int MODE, int FLAGS>
 __global__ STGV_STEP_BOUNDS void lbm_step_kernel(T* pop, T* dst, Geometry geo,
                                                        PhysConsts c, float* __restrict__ fields,
                                                        double* __restrict__ partials) {
   const int n = geo.n;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  const int z = blockIdx.z;
+  const BlockXYZ blk = node_block<MODE>();
+  const int x = blk.bx * blockDim.x + threadIdx.x;
+  const int y = blk.by * blockDim.y + threadIdx.y;
+  const int z = blk.bz;
   const bool active = (x < n) && (y < n);
   constexpr bool kPart = (FLAGS & K_PARTIALS) != 0;
   if (!kPart && !active) return;
@@ -57,8 +83,8 @@ __global__ STGV_STEP_BOUNDS void lbm_step_kernel(T* pop, T* dst, Geometry geo,
     }
   }
   if (kPart) {
-    const int64_t blk = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
-    block_reduce_store<NPART, (1u << P_UMAX2)>(acc, partials + blk * NPART);
+    const int64_t b = blk.bx + (int64_t)gridDim.x * (blk.by + (int64_t)gridDim.y * blk.bz);
+    block_reduce_store<NPART, (1u << P_UMAX2)>(acc, partials + b * NPART);
   }
 }
 
@@ -70,9 +96,10 @@ __global__ STGV_STEP_BOUNDS void lbm_step_xstaged_kernel(T* pop, Geometry geo, P
   constexpr int KF = x_moving<QF>(), KG = x_moving<QG>();
   __shared__ T xs[KF + KG][256];
   const int n = geo.n;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  const NodeIndex ix = make_index(x, y, blockIdx.z, n);
+  const BlockXYZ blk = node_block<MODE_ODD>();
+  const int x = blk.bx * blockDim.x + threadIdx.x;
+  const int y = blk.by * blockDim.y + threadIdx.y;
+  const NodeIndex ix = make_index(x, y, blk.bz, n);
   C f[QF], g[QG];
   gather<QF, T, MODE_ODD>(f, pop, 0, ix, geo.stride);
   gather<QG, T, MODE_ODD>(g, pop, QF, ix, geo.stride);
