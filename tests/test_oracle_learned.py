@@ -217,3 +217,29 @@ def test_forward_pass_of_a_hand_computed_network():
         want[7] = -0.3
         assert np.allclose(out[r], want, rtol=0, atol=1e-15), (r, out[r][[0, 7, 40]], want[[0, 7, 40]])
     assert abs(out[0, 0]) > 1.5          # large enough that a tanh on the output would show
+
+
+def test_normalisation_statistics_of_known_columns():
+    # columns with exactly known statistics: a +- d alternating (mean a, standard deviation
+    # d), a constant column (scale 0), targets of root mean square r, and a zero target
+    # column (scale 1): a variance taken with the wrong mean, a missing square root or an
+    # inverted scale fails
+    n = 64
+    sign = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    x = np.zeros((n, L.N_IN))
+    y = np.zeros((n, L.N_OUT))
+    for k in range(L.N_IN):
+        x[:, k] = 0.25 * k - 3.0 + (0.5 + 0.125 * k) * sign
+    x[:, 5] = 7.0
+    for k in range(L.N_OUT - 1):
+        y[:, k] = (1.0 + k) * 1e-4 * sign
+    mean, iscale, yscale = L.norm_from_data(x, y)
+    for k in range(L.N_IN):
+        assert mean[k] == pytest.approx(0.25 * k - 3.0 if k != 5 else 7.0, abs=1e-13)
+        if k == 5:
+            assert iscale[k] == 0.0
+        else:
+            assert iscale[k] == pytest.approx(1.0 / (0.5 + 0.125 * k), rel=1e-12)
+    for k in range(L.N_OUT - 1):
+        assert yscale[k] == pytest.approx((1.0 + k) * 1e-4, rel=1e-12)
+    assert yscale[L.N_OUT - 1] == 1.0
