@@ -57,7 +57,7 @@ def read_traffic(workload_key, n3, bytes_per_node):
     if kv.get("source_hash") != kernel_source_hash():
         return None, "counters predate the current kernel sources"
     try:
-        return float(kv["hbm_bytes_per_launch"]), path
+        return float(kv["hbm_bytes_per_launch"]), os.path.relpath(path, ROOT)
     except (KeyError, ValueError):
         return None, "malformed counter summary"
 
