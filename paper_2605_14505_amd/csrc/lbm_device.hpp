@@ -16,6 +16,7 @@
 // order.  MODE_AB is a two-lattice push variant (read natural at x, write
 // natural at x + e_i into a second array) kept for bitwise cross-checking.
 #pragma once
+#include <utility>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -71,21 +72,29 @@ struct Geometry {
 // ---------------------------------------------------------------------------
 struct bf16_t { uint16_t bits; };
 
-#ifndef STGV_NT_LOAD
-#define STGV_NT_LOAD 0
+// Population loads that bypass the caches, per layout mode (bit MODE of the mask), and in
+// the odd step for the directions with e_x = 0 (whose lines no neighbouring wavefront
+// shares) where the kernel asks for it.  Every value is read once per step; measured on
+// gfx950 (256^3 D3Q27 x D3Q19, FP32 / FP16 storage), non-temporal loads of the even step
+// and of the odd step's x-aligned directions take 7-8 % off both steps, while
+// non-temporal loads of the x-shifted directions, whose lines two wavefronts share, make
+// the odd step 20-30 % slower.  The odd step of 2-byte storage at 512^3, whose x-moving
+// stores go through LDS, is 4 % slower with them and keeps cached loads.
+#ifndef STGV_NT_LOAD_MODES
+#define STGV_NT_LOAD_MODES 1
 #endif
-template <typename T>
+#ifndef STGV_NT_LOAD_ODD_XALIGNED
+#define STGV_NT_LOAD_ODD_XALIGNED 1
+#endif
+template <bool NT, typename T>
 __device__ __forceinline__ T get(const T* p) {
-#if STGV_NT_LOAD
-  return __builtin_nontemporal_load(p);
-#else
-  return *p;
-#endif
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
 }
-template <typename C> __device__ __forceinline__ C load_as(const float* p) { return (C)get(p); }
-template <typename C> __device__ __forceinline__ C load_as(const _Float16* p) { return (C)(float)get(p); }
-template <typename C> __device__ __forceinline__ C load_as(const bf16_t* p) {
-  return (C)__uint_as_float(((uint32_t)get(&p->bits)) << 16);
+template <typename C, bool NT = false> __device__ __forceinline__ C load_as(const float* p) { return (C)get<NT>(p); }
+template <typename C, bool NT = false> __device__ __forceinline__ C load_as(const _Float16* p) { return (C)(float)get<NT>(p); }
+template <typename C, bool NT = false> __device__ __forceinline__ C load_as(const bf16_t* p) {
+  return (C)__uint_as_float(((uint32_t)get<NT>(&p->bits)) << 16);
 }
 
 // Population stores bypass the caches by default (each value is read again only
@@ -153,19 +162,46 @@ __device__ __forceinline__ T* at_node(T* array, uint32_t node) {
 }
 
 // Gather the pre-collision populations of one lattice (Q directions starting at
-// array `first`) in the layout given by MODE.
-template <int Q, typename T, int MODE, typename C>
+// array `first`) in the layout given by MODE.  The direction is a compile-time index, so
+// the choice of load (cached or non-temporal) is fixed per direction.
+template <int Q, typename T, int MODE, bool NTX, int I, typename C>
+__device__ __forceinline__ void gather_one(C* v, const T* pop, int first, const NodeIndex& ix,
+                                           int64_t stride) {
+  using S = Stencil<Q>;
+  constexpr bool odd = MODE == MODE_ODD;   // post-collision value of x - e_i sits in slot opp(i)
+  constexpr bool nt = ((STGV_NT_LOAD_MODES >> MODE) & 1) != 0 ||
+                      (odd && NTX && STGV_NT_LOAD_ODD_XALIGNED && S::ex[I] == 0);
+  const uint32_t off = odd ? ix.at(-S::ex[I], -S::ey[I], -S::ez[I]) : ix.base;
+  const int slot = odd ? opp(I) : I;
+  v[I] = load_as<C, nt>(at_node(pop + (int64_t)(first + slot) * stride, off));
+}
+template <int Q, typename T, int MODE, bool NTX, typename C, int... I>
+__device__ __forceinline__ void gather_seq(C* v, const T* pop, int first, const NodeIndex& ix,
+                                           int64_t stride, std::integer_sequence<int, I...>) {
+  (gather_one<Q, T, MODE, NTX, I>(v, pop, first, ix, stride), ...);
+}
+// NTX: non-temporal loads for the odd step's x-aligned directions.
+template <int Q, typename T, int MODE, bool NTX = false, typename C>
 __device__ __forceinline__ void gather(C* v, const T* pop, int first, const NodeIndex& ix,
                                        int64_t stride) {
+  gather_seq<Q, T, MODE, NTX>(v, pop, first, ix, stride, std::make_integer_sequence<int, Q>{});
+}
+
+// The same gather as a loop over directions with cached loads, for the LDS-staged odd step:
+// there the compiler's schedule of this form is the faster one (512^3 FP16 odd step
+// 5.45 -> 5.25 ms on gfx950).
+template <int Q, typename T, int MODE, typename C>
+__device__ __forceinline__ void gather_loop(C* v, const T* pop, int first, const NodeIndex& ix,
+                                            int64_t stride) {
   using S = Stencil<Q>;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     uint32_t off;
     int slot;
-    if (MODE == MODE_ODD) {          // post-collision value of x - e_i sits in slot opp(i)
+    if (MODE == MODE_ODD) {
       off = ix.at(-S::ex[i], -S::ey[i], -S::ez[i]);
       slot = opp(i);
-    } else {                         // natural order
+    } else {
       off = ix.base;
       slot = i;
     }
@@ -173,24 +209,27 @@ __device__ __forceinline__ void gather(C* v, const T* pop, int first, const Node
   }
 }
 
-// Scatter post-collision populations for MODE (AB writes into `dst`).
+// Scatter post-collision populations for MODE (AB writes into `dst`), one compile-time
+// direction at a time like gather.
+template <int Q, typename T, int MODE, int I, typename C>
+__device__ __forceinline__ void scatter_one(const C* v, T* dst, int first, const NodeIndex& ix,
+                                            int64_t stride) {
+  using S = Stencil<Q>;
+  constexpr bool even = MODE == MODE_EVEN;   // even: kept at x, swapped into slot opp(i);
+                                             // odd / AB push: natural slot i at x + e_i
+  const uint32_t off = even ? ix.base : ix.at(S::ex[I], S::ey[I], S::ez[I]);
+  const int slot = even ? opp(I) : I;
+  store_as(at_node(dst + (int64_t)(first + slot) * stride, off), v[I]);
+}
+template <int Q, typename T, int MODE, typename C, int... I>
+__device__ __forceinline__ void scatter_seq(const C* v, T* dst, int first, const NodeIndex& ix,
+                                            int64_t stride, std::integer_sequence<int, I...>) {
+  (scatter_one<Q, T, MODE, I>(v, dst, first, ix, stride), ...);
+}
 template <int Q, typename T, int MODE, typename C>
 __device__ __forceinline__ void scatter(const C* v, T* dst, int first, const NodeIndex& ix,
                                         int64_t stride) {
-  using S = Stencil<Q>;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    uint32_t off;
-    int slot;
-    if (MODE == MODE_EVEN) {         // keep at x, swapped into slot opp(i)
-      off = ix.base;
-      slot = opp(i);
-    } else {                         // odd / AB push: natural slot i at x + e_i
-      off = ix.at(S::ex[i], S::ey[i], S::ez[i]);
-      slot = i;
-    }
-    store_as(at_node(dst + (int64_t)(first + slot) * stride, off), v[i]);
-  }
+  scatter_seq<Q, T, MODE>(v, dst, first, ix, stride, std::make_integer_sequence<int, Q>{});
 }
 
 // ---------------------------------------------------------------------------

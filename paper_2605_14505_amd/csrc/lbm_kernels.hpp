@@ -12,15 +12,23 @@ namespace stgv {
 // AB destination and equals `pop` otherwise.
 // ---------------------------------------------------------------------------
 // Minimum resident 256-thread blocks per CU requested from the register allocator
-// (0 = compiler's choice).
+// (0 = compiler's choice): STGV_EVEN_MIN_BLOCKS for the plain even step with 4-byte
+// storage and arithmetic (the instance that fits a tighter register budget without
+// spilling), STGV_STEP_MIN_BLOCKS for every other step instance.
 #ifndef STGV_STEP_MIN_BLOCKS
 #define STGV_STEP_MIN_BLOCKS 0
 #endif
-#if STGV_STEP_MIN_BLOCKS > 0
-#define STGV_STEP_BOUNDS __launch_bounds__(256, STGV_STEP_MIN_BLOCKS)
-#else
-#define STGV_STEP_BOUNDS __launch_bounds__(256)
+#ifndef STGV_EVEN_MIN_BLOCKS
+#define STGV_EVEN_MIN_BLOCKS STGV_STEP_MIN_BLOCKS
 #endif
+template <int MODE, int FLAGS, typename T, typename C>
+constexpr int step_min_blocks() {
+  const int b = (MODE == MODE_EVEN && FLAGS == K_COLLIDE && sizeof(T) == 4 && sizeof(C) == 4)
+                    ? STGV_EVEN_MIN_BLOCKS : STGV_STEP_MIN_BLOCKS;
+  return b > 0 ? b : 1;
+}
+#define STGV_STEP_BOUNDS_FOR(MODE, FLAGS, T, C) __launch_bounds__(256, (step_min_blocks<MODE, FLAGS, T, C>()))
+#define STGV_STEP_BOUNDS STGV_STEP_BOUNDS_FOR(MODE_ODD, K_COLLIDE, T, C)
 
 // Block coordinates of a node kernel.  The hardware hands consecutive workgroups to the
 // 8 XCDs in turn, each with its own L2, so the blocks that split one row along x sit on
@@ -48,7 +56,7 @@ __device__ __forceinline__ BlockXYZ node_block() {
 }
 
 template <int QF, int QG, int FORCE, typename T, typename C, int MODE, int FLAGS>
-__global__ STGV_STEP_BOUNDS void lbm_step_kernel(T* pop, T* dst, Geometry geo,
+__global__ STGV_STEP_BOUNDS_FOR(MODE, FLAGS, T, C) void lbm_step_kernel(T* pop, T* dst, Geometry geo,
                                                        PhysConsts c, float* __restrict__ fields,
                                                        double* __restrict__ partials) {
   const int n = geo.n;
@@ -67,8 +75,8 @@ __global__ STGV_STEP_BOUNDS void lbm_step_kernel(T* pop, T* dst, Geometry geo,
   if (active) {
     const NodeIndex ix = make_index(x, y, z, n);
     C f[QF], g[QG];
-    gather<QF, T, MODE>(f, pop, 0, ix, geo.stride);
-    gather<QG, T, MODE>(g, pop, QF, ix, geo.stride);
+    gather<QF, T, MODE, true>(f, pop, 0, ix, geo.stride);
+    gather<QG, T, MODE, true>(g, pop, QF, ix, geo.stride);
     StepMacro<C> m;
     step_macro<QF, QG, FORCE, sizeof(T) == 4>(f, g, c, m);
     if (FLAGS & (K_FIELDS | K_PARTIALS)) {
@@ -101,8 +109,8 @@ __global__ STGV_STEP_BOUNDS void lbm_step_xstaged_kernel(T* pop, Geometry geo, P
   const int y = blk.by * blockDim.y + threadIdx.y;
   const NodeIndex ix = make_index(x, y, blk.bz, n);
   C f[QF], g[QG];
-  gather<QF, T, MODE_ODD>(f, pop, 0, ix, geo.stride);
-  gather<QG, T, MODE_ODD>(g, pop, QF, ix, geo.stride);
+  gather_loop<QF, T, MODE_ODD>(f, pop, 0, ix, geo.stride);
+  gather_loop<QG, T, MODE_ODD>(g, pop, QF, ix, geo.stride);
   StepMacro<C> m;
   step_macro<QF, QG, FORCE, sizeof(T) == 4>(f, g, c, m);
   step_collide<QF, QG, FORCE, sizeof(T) == 4>(f, g, c, m);
