@@ -10,8 +10,9 @@ diagnostic steps, the dissipation stencil and the final reduction).
 
 Prints ONE JSON line: MLUPS (whole job), ms per step, the roofline of the step
 kernel (algorithmic bytes 2 (Q_f + Q_g) b per node over its HIP-event-timed
-average duration, against the 8 TB/s HBM peak), the streaming-copy ceiling,
-the HBM traffic read from the committed rocprofv3 counter summary when it was
+average duration, against the 8 TB/s HBM peak), the streaming-copy ceiling, the
+ceiling of the step's own access pattern (free streaming: the same loads, stores,
+launch shapes and block order with no collision), the HBM traffic read from the committed rocprofv3 counter summary when it was
 taken on the current kernel sources, the FP64 oracle timed on the host cores
 (the only part of this script that runs the oracle), and the error of the GPU's
 energy and dissipation histories against the oracle's stored 64^3 histories.
@@ -396,6 +397,18 @@ def main():
     copy_gbs = 2 * nbytes * reps / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
     del a, b
 
+    # ---- the step's own access pattern: free streaming (same loads, stores, launch
+    # shapes and block order, identity collision) on a state of the same configuration
+    sim = stgv.Simulation(diag_every=0, **common)
+    sim.free_stream(W + W % 2)
+    ev0.record(stream)
+    sim.free_stream(K + K % 2)
+    ev1.record(stream)
+    ev1.synchronize()
+    pattern_gbs = bytes_per_node * n3 * (K + K % 2) / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    sim.close()
+    del sim
+
     key = f"step_{n}_{args.q_f}x{args.q_g}_{args.storage}_{args.compute}_{args.forcing}"
     traffic, traffic_src = read_traffic(key, n3, bytes_per_node)
 
@@ -434,6 +447,8 @@ def main():
             "step_mlups": round(n3 / (kernel_ms * 1e-3) / 1e6, 1),
             "copy_ceiling_gbs": round(copy_gbs, 1),
             "frac_of_copy": round(achieved / copy_gbs, 4),
+            "pattern_ceiling_gbs": round(pattern_gbs, 1),
+            "frac_of_pattern": round(achieved / pattern_gbs, 4),
             "traffic_source": traffic_src,
         },
     }

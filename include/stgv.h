@@ -138,6 +138,15 @@ int lbm_init_tgv(const lbm_params* p, void* pop_dev, size_t pop_bytes, void* wor
  * ring (4096 records); drain it with lbm_diagnostics. */
 int lbm_step(lbm_ctx* ctx, int64_t n);
 
+/* Queue n >= 0 free-streaming steps: the streaming half of Eqs. (5) and (11)
+ * alone (no collision, no force), with the step's own loads, stores, launch
+ * shape and block order.  Every population moves one link along its velocity
+ * per step, exactly (values are moved, never rounded), and the step counter
+ * and layout parity advance as in lbm_step.  Afterwards the state is no longer
+ * the method's; the call measures the memory-access ceiling of the step and
+ * checks the streaming layout.  Queues no diagnostics. */
+int lbm_stream(lbm_ctx* ctx, int64_t n);
+
 /* Queue a diagnostic record of the current state (without stepping). */
 int lbm_sample(lbm_ctx* ctx);
 

@@ -102,6 +102,25 @@ hipError_t launch_init<STGV_T>(int qf, int qg, const LaunchShape& sh, hipStream_
 }
 
 template <>
+hipError_t launch_stream<STGV_T>(int qf, int qg, int mode, const LaunchShape& sh, hipStream_t st,
+                                 STGV_T* pop, STGV_T* dst, Geometry geo) {
+  const bool staged = sizeof(STGV_T) == 2 && mode == MODE_ODD && xstaged_shape(sh, geo.n);
+#define STGV_STREAM(A, B) \
+  if (qf == A && qg == B) { \
+    if (staged) { \
+      if constexpr (sizeof(STGV_T) == 2) \
+        hipLaunchKernelGGL((lbm_stream_xstaged_kernel<A, B, STGV_T>), sh.grid, sh.block, 0, st, pop, geo); \
+    } else if (mode == MODE_EVEN) hipLaunchKernelGGL((lbm_stream_kernel<A, B, STGV_T, MODE_EVEN>), sh.grid, sh.block, 0, st, pop, dst, geo); \
+    else if (mode == MODE_ODD) hipLaunchKernelGGL((lbm_stream_kernel<A, B, STGV_T, MODE_ODD>), sh.grid, sh.block, 0, st, pop, dst, geo); \
+    else if (mode == MODE_AB) hipLaunchKernelGGL((lbm_stream_kernel<A, B, STGV_T, MODE_AB>), sh.grid, sh.block, 0, st, pop, dst, geo); \
+    else return hipErrorInvalidValue; \
+    return hipGetLastError(); }
+  STGV_FOR_EACH_PAIR(STGV_STREAM)
+#undef STGV_STREAM
+  return hipErrorInvalidValue;
+}
+
+template <>
 hipError_t launch_canon<STGV_T>(int qf, int qg, int mode, const LaunchShape& sh, hipStream_t st,
                                 const STGV_T* pop, Geometry geo, float* out) {
 #define STGV_CANON(A, B) \

@@ -123,6 +123,50 @@ __global__ STGV_STEP_BOUNDS void lbm_step_xstaged_kernel(T* pop, Geometry geo, P
 }
 
 // ---------------------------------------------------------------------------
+// Free streaming: the step's loads, stores, launch shape and block order with the
+// identity in place of the collision, so every population moves one link along its
+// velocity per call (the streaming half of Eqs. (5) and (11) alone).  Values pass
+// through FP32, which holds every FP16 / BF16 value exactly, so a stream is exact in
+// every storage type.  It is the ceiling of the step's own access pattern.
+// ---------------------------------------------------------------------------
+template <int QF, int QG, typename T, int MODE>
+__global__ __launch_bounds__(256) void lbm_stream_kernel(T* pop, T* dst, Geometry geo) {
+  const int n = geo.n;
+  const BlockXYZ blk = node_block<MODE>();
+  const int x = blk.bx * blockDim.x + threadIdx.x;
+  const int y = blk.by * blockDim.y + threadIdx.y;
+  if (x >= n || y >= n) return;
+  const NodeIndex ix = make_index(x, y, blk.bz, n);
+  float f[QF], g[QG];
+  gather<QF, T, MODE, true>(f, pop, 0, ix, geo.stride);
+  gather<QG, T, MODE, true>(g, pop, QF, ix, geo.stride);
+  scatter<QF, T, MODE>(f, dst, 0, ix, geo.stride);
+  scatter<QG, T, MODE>(g, dst, QF, ix, geo.stride);
+}
+
+// The odd free-streaming step with the x-shifted stores staged through LDS, on the
+// launch shapes where the odd step of 2-byte storage is staged (every lane active).
+template <int QF, int QG, typename T>
+__global__ __launch_bounds__(256) void lbm_stream_xstaged_kernel(T* pop, Geometry geo) {
+  constexpr int KF = x_moving<QF>(), KG = x_moving<QG>();
+  __shared__ T xs[KF + KG][256];
+  const int n = geo.n;
+  const BlockXYZ blk = node_block<MODE_ODD>();
+  const int x = blk.bx * blockDim.x + threadIdx.x;
+  const int y = blk.by * blockDim.y + threadIdx.y;
+  const NodeIndex ix = make_index(x, y, blk.bz, n);
+  float f[QF], g[QG];
+  gather_loop<QF, T, MODE_ODD>(f, pop, 0, ix, geo.stride);
+  gather_loop<QG, T, MODE_ODD>(g, pop, QF, ix, geo.stride);
+  const XLane l = make_xlane();
+  stage_x<QF>(f, xs, 0, l);
+  stage_x<QG>(g, xs, KF, l);
+  __syncthreads();
+  scatter_staged<QF>(f, pop, 0, ix, geo.stride, xs, 0, l);
+  scatter_staged<QG>(g, pop, QF, ix, geo.stride, xs, KF, l);
+}
+
+// ---------------------------------------------------------------------------
 // Taylor-Green initial state (Eqs. (20)-(21)) in natural order.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {

@@ -68,6 +68,11 @@ template <typename T>
 hipError_t launch_init(int qf, int qg, const LaunchShape& sh, hipStream_t st, T* pop, Geometry geo,
                        double u0, double noise_amp, uint64_t seed);
 
+// Free streaming (lbm_stream_kernel) in layout MODE, from pop into dst.
+template <typename T>
+hipError_t launch_stream(int qf, int qg, int mode, const LaunchShape& sh, hipStream_t st, T* pop,
+                         T* dst, Geometry geo);
+
 template <typename T>
 hipError_t launch_canon(int qf, int qg, int mode, const LaunchShape& sh, hipStream_t st,
                         const T* pop, Geometry geo, float* out);

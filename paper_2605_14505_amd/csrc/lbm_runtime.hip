@@ -606,6 +606,31 @@ int lbm_step(lbm_ctx* c, int64_t nsteps) {
   return LBM_OK;
 }
 
+int lbm_stream(lbm_ctx* c, int64_t nsteps) {
+  if (!c) { set_err(g_err, "ctx is NULL"); return LBM_EINVAL; }
+  if (nsteps < 0) { set_err(c->err, "n = %lld < 0", (long long)nsteps); return LBM_EINVAL; }
+  for (int64_t s = 0; s < nsteps; ++s) {
+    int mode;
+    char *src, *dst;
+    if (c->p.layout == LBM_LAYOUT_AB) {
+      mode = MODE_AB;
+      src = c->odd ? c->pop_b : c->pop;
+      dst = c->odd ? c->pop : c->pop_b;
+    } else {
+      mode = c->odd ? MODE_ODD : MODE_EVEN;
+      src = dst = c->pop;
+    }
+    hipError_t e = by_storage(c->p.storage, [&](auto* tag) {
+      using T = std::remove_pointer_t<decltype(tag)>;
+      return launch_stream<T>(c->p.q_f, c->p.q_g, mode, c->sh, c->stream, (T*)src, (T*)dst, c->geo);
+    });
+    if (e != hipSuccess) return hip_fail(c, e, "free-streaming kernel");
+    c->step++;
+    c->odd ^= 1;
+  }
+  return LBM_OK;
+}
+
 int lbm_sample(lbm_ctx* c) {
   if (!c) { set_err(g_err, "ctx is NULL"); return LBM_EINVAL; }
   if (c->ring_head - c->ring_tail + 1 > kRingCap) {

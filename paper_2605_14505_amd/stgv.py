@@ -74,6 +74,7 @@ def _load():
         "lbm_derived": (ctypes.c_int, [P(lbm_params), P(dbl)]),
         "lbm_init_tgv": (ctypes.c_int, [P(lbm_params), vp, sz, vp, sz, vp, P(vp)]),
         "lbm_step": (ctypes.c_int, [vp, i64]),
+        "lbm_stream": (ctypes.c_int, [vp, i64]),
         "lbm_sample": (ctypes.c_int, [vp]),
         "lbm_diagnostics": (ctypes.c_int, [vp, P(lbm_diag), i32, P(i32)]),
         "lbm_read_fields": (ctypes.c_int, [vp, vp]),
@@ -109,7 +110,7 @@ def _load():
 
 
 LIB = _load()
-EXPORTED = ("lbm_query_sizes", "lbm_derived", "lbm_init_tgv", "lbm_step", "lbm_sample",
+EXPORTED = ("lbm_query_sizes", "lbm_derived", "lbm_init_tgv", "lbm_step", "lbm_stream", "lbm_sample",
             "lbm_diagnostics", "lbm_read_fields", "lbm_read_populations", "lbm_load_populations",
             "lbm_stencil_info", "lbm_bw_probe", "lbm_get_step", "lbm_last_error",
             "lbm_status_string", "lbm_destroy", "lbm_mlp_packed_bytes", "lbm_mlp_pack",
@@ -172,6 +173,10 @@ def lbm_init_tgv(p, pop, work, stream):
 
 def lbm_step(ctx, n):
     _check(LIB.lbm_step(ctx, n), ctx)
+
+
+def lbm_stream(ctx, n):
+    _check(LIB.lbm_stream(ctx, n), ctx)
 
 
 def lbm_sample(ctx):
@@ -326,6 +331,10 @@ class Simulation:
 
     def step(self, n=1):
         lbm_step(self.ctx, n)
+
+    def free_stream(self, n=1):
+        """Free streaming (no collision): a measurement and layout check, not the method."""
+        lbm_stream(self.ctx, n)
 
     def sample(self):
         lbm_sample(self.ctx)
