@@ -313,6 +313,89 @@ __device__ __forceinline__ void scatter_staged(const C* v, T* dst, int first, co
 }
 
 // ---------------------------------------------------------------------------
+// Row-aligned odd step (blocks of whole rows)
+//
+// Where a block holds whole rows of the box (its x extent is n), the odd step's
+// x-shift of +-1 never leaves the block.  Every lane then loads and stores only at its
+// own x: the values of the directions with e_x != 0 are loaded at x from the row of
+// (y - e_y, z - e_z) and left in LDS, and after a barrier lane x takes what lane
+// x - e_x of its row loaded (wrapped within the row); the post-collision values go the
+// other way, lane x leaving its value at x + e_x and storing, after a barrier, what was
+// left at its own place.  All global accesses are whole aligned lines and no line is
+// shared between wavefronts, so every load bypasses the caches.
+// ---------------------------------------------------------------------------
+template <int Q>
+constexpr int x_slot(int i) {     // index of direction i among those with e_x != 0
+  int k = 0;
+  for (int j = 0; j < i; ++j) k += Stencil<Q>::ex[j] != 0;
+  return k;
+}
+
+__device__ __forceinline__ float rounded(const float*, float v) { return v; }
+__device__ __forceinline__ void put_rounded(float* p, float v) { put(p, v); }
+__device__ __forceinline__ float raw_load_nt(const float* p) { return get<true>(p); }
+__device__ __forceinline__ _Float16 raw_load_nt(const _Float16* p) { return get<true>(p); }
+__device__ __forceinline__ bf16_t raw_load_nt(const bf16_t* p) { return bf16_t{get<true>(&p->bits)}; }
+
+struct RowLane {
+  int lid;      // thread index in the block, = row * n + x
+  int row0;     // lid - x: the start of the lane's row in the block
+  int xm, xp;   // x - 1 and x + 1, wrapped within the row
+};
+
+template <int Q, typename T, int I, typename C>
+__device__ __forceinline__ void row_load_one(C* v, T (*xs)[256], int k0, const T* pop, int first,
+                                             const NodeIndex& ix, int64_t stride, const RowLane& l) {
+  using S = Stencil<Q>;
+  const T* p = at_node(pop + (int64_t)(first + opp(I)) * stride, ix.at(0, -S::ey[I], -S::ez[I]));
+  if constexpr (S::ex[I] == 0) v[I] = load_as<C, true>(p);
+  else xs[k0 + x_slot<Q>(I)][l.lid] = raw_load_nt(p);
+}
+template <int Q, typename T, int I, typename C>
+__device__ __forceinline__ void row_pick_one(C* v, const T (*xs)[256], int k0, const RowLane& l) {
+  using S = Stencil<Q>;
+  if constexpr (S::ex[I] != 0)
+    v[I] = load_as<C>(&xs[k0 + x_slot<Q>(I)][l.row0 + (S::ex[I] > 0 ? l.xm : l.xp)]);
+}
+template <int Q, typename T, int I, typename C>
+__device__ __forceinline__ void row_put_one(const C* v, T (*xs)[256], int k0, const RowLane& l) {
+  using S = Stencil<Q>;
+  if constexpr (S::ex[I] != 0)
+    xs[k0 + x_slot<Q>(I)][l.row0 + (S::ex[I] > 0 ? l.xp : l.xm)] = rounded((const T*)nullptr, v[I]);
+}
+template <int Q, typename T, int I, typename C>
+__device__ __forceinline__ void row_store_one(const C* v, const T (*xs)[256], int k0, T* dst, int first,
+                                              const NodeIndex& ix, int64_t stride, const RowLane& l) {
+  using S = Stencil<Q>;
+  T* p = at_node(dst + (int64_t)(first + I) * stride, ix.at(0, S::ey[I], S::ez[I]));
+  if constexpr (S::ex[I] == 0) store_as(p, v[I]);
+  else put_rounded(p, xs[k0 + x_slot<Q>(I)][l.lid]);
+}
+
+template <int Q, typename T, typename C, int... I>
+__device__ __forceinline__ void row_load(C* v, T (*xs)[256], int k0, const T* pop, int first,
+                                         const NodeIndex& ix, int64_t stride, const RowLane& l,
+                                         std::integer_sequence<int, I...>) {
+  (row_load_one<Q, T, I>(v, xs, k0, pop, first, ix, stride, l), ...);
+}
+template <int Q, typename T, typename C, int... I>
+__device__ __forceinline__ void row_pick(C* v, const T (*xs)[256], int k0, const RowLane& l,
+                                         std::integer_sequence<int, I...>) {
+  (row_pick_one<Q, T, I>(v, xs, k0, l), ...);
+}
+template <int Q, typename T, typename C, int... I>
+__device__ __forceinline__ void row_put(const C* v, T (*xs)[256], int k0, const RowLane& l,
+                                        std::integer_sequence<int, I...>) {
+  (row_put_one<Q, T, I>(v, xs, k0, l), ...);
+}
+template <int Q, typename T, typename C, int... I>
+__device__ __forceinline__ void row_store(const C* v, const T (*xs)[256], int k0, T* dst, int first,
+                                          const NodeIndex& ix, int64_t stride, const RowLane& l,
+                                          std::integer_sequence<int, I...>) {
+  (row_store_one<Q, T, I>(v, xs, k0, dst, first, ix, stride, l), ...);
+}
+
+// ---------------------------------------------------------------------------
 // node-local physics
 // ---------------------------------------------------------------------------
 // Moments over a lattice whose directions come in opposite pairs (i, i + 1):

@@ -122,6 +122,40 @@ __global__ STGV_STEP_BOUNDS void lbm_step_xstaged_kernel(T* pop, Geometry geo, P
   scatter_staged<QG>(g, pop, QF, ix, geo.stride, xs, KF, l);
 }
 
+// The plain odd step on blocks of whole rows, all loads and stores row-aligned with the
+// x-shift taken through LDS (row_load / row_pick / row_put / row_store).  Launched only on
+// shapes whose blocks hold whole rows and tile the box exactly (rowshift_shape), so every
+// lane is active and reaches the barriers.
+template <int QF, int QG, int FORCE, typename T, typename C>
+__global__ STGV_STEP_BOUNDS void lbm_step_rowshift_kernel(T* pop, Geometry geo, PhysConsts c) {
+  constexpr int KF = x_moving<QF>(), KG = x_moving<QG>();
+  __shared__ T xs[KF + KG][256];
+  const int n = geo.n;
+  const int x = threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const NodeIndex ix = make_index(x, y, blockIdx.z, n);
+  RowLane l;
+  l.lid = threadIdx.y * blockDim.x + x;
+  l.row0 = l.lid - x;
+  l.xm = (int)ix.xo[0];
+  l.xp = (int)ix.xo[2];
+  C f[QF], g[QG];
+  row_load<QF>(f, xs, 0, pop, 0, ix, geo.stride, l, std::make_integer_sequence<int, QF>{});
+  row_load<QG>(g, xs, KF, pop, QF, ix, geo.stride, l, std::make_integer_sequence<int, QG>{});
+  __syncthreads();
+  row_pick<QF>(f, (const T(*)[256])xs, 0, l, std::make_integer_sequence<int, QF>{});
+  row_pick<QG>(g, (const T(*)[256])xs, KF, l, std::make_integer_sequence<int, QG>{});
+  __syncthreads();                      // every lane has taken its values before any put
+  StepMacro<C> m;
+  step_macro<QF, QG, FORCE, sizeof(T) == 4>(f, g, c, m);
+  step_collide<QF, QG, FORCE, sizeof(T) == 4>(f, g, c, m);
+  row_put<QF>(f, xs, 0, l, std::make_integer_sequence<int, QF>{});
+  row_put<QG>(g, xs, KF, l, std::make_integer_sequence<int, QG>{});
+  __syncthreads();
+  row_store<QF>(f, (const T(*)[256])xs, 0, pop, 0, ix, geo.stride, l, std::make_integer_sequence<int, QF>{});
+  row_store<QG>(g, (const T(*)[256])xs, KF, pop, QF, ix, geo.stride, l, std::make_integer_sequence<int, QG>{});
+}
+
 // ---------------------------------------------------------------------------
 // Free streaming: the step's loads, stores, launch shape and block order with the
 // identity in place of the collision, so every population moves one link along its
@@ -142,6 +176,34 @@ __global__ __launch_bounds__(256) void lbm_stream_kernel(T* pop, T* dst, Geometr
   gather<QG, T, MODE, true>(g, pop, QF, ix, geo.stride);
   scatter<QF, T, MODE>(f, dst, 0, ix, geo.stride);
   scatter<QG, T, MODE>(g, dst, QF, ix, geo.stride);
+}
+
+// The odd free-streaming step row-aligned, on the shapes where the odd step of 2-byte
+// storage runs row-aligned (every lane active).
+template <int QF, int QG, typename T>
+__global__ __launch_bounds__(256) void lbm_stream_rowshift_kernel(T* pop, Geometry geo) {
+  constexpr int KF = x_moving<QF>(), KG = x_moving<QG>();
+  __shared__ T xs[KF + KG][256];
+  const int n = geo.n;
+  const int x = threadIdx.x;
+  const NodeIndex ix = make_index(x, blockIdx.y * blockDim.y + threadIdx.y, blockIdx.z, n);
+  RowLane l;
+  l.lid = threadIdx.y * blockDim.x + x;
+  l.row0 = l.lid - x;
+  l.xm = (int)ix.xo[0];
+  l.xp = (int)ix.xo[2];
+  float f[QF], g[QG];
+  row_load<QF>(f, xs, 0, pop, 0, ix, geo.stride, l, std::make_integer_sequence<int, QF>{});
+  row_load<QG>(g, xs, KF, pop, QF, ix, geo.stride, l, std::make_integer_sequence<int, QG>{});
+  __syncthreads();
+  row_pick<QF>(f, (const T(*)[256])xs, 0, l, std::make_integer_sequence<int, QF>{});
+  row_pick<QG>(g, (const T(*)[256])xs, KF, l, std::make_integer_sequence<int, QG>{});
+  __syncthreads();
+  row_put<QF>(f, xs, 0, l, std::make_integer_sequence<int, QF>{});
+  row_put<QG>(g, xs, KF, l, std::make_integer_sequence<int, QG>{});
+  __syncthreads();
+  row_store<QF>(f, (const T(*)[256])xs, 0, pop, 0, ix, geo.stride, l, std::make_integer_sequence<int, QF>{});
+  row_store<QG>(g, (const T(*)[256])xs, KF, pop, QF, ix, geo.stride, l, std::make_integer_sequence<int, QG>{});
 }
 
 // The odd free-streaming step with the x-shifted stores staged through LDS, on the

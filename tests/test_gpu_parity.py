@@ -268,6 +268,22 @@ def test_aa_equals_ab_bitwise(storage):
         assert torch.equal(aa.fields(), ab.fields()), n
 
 
+@pytest.mark.parametrize("storage,n", [("fp16", 128), ("bf16", 128), ("fp16", 256), ("bf16", 256)])
+def test_aa_equals_ab_bitwise_whole_row_blocks(storage, n):
+    # 2-byte storage on blocks of whole rows that tile the box: the odd AA step runs
+    # row-aligned, its x-shift taken through LDS; the A-B push does not, so equality pins
+    # it bit for bit
+    kw = c1_kw(n=n, forcing="shift", storage=storage, g_over_n=0.02)
+    aa = gpu_sim(layout="aa", **kw)
+    ab = gpu_sim(layout="ab", **kw)
+    for k in (1, 2, 7):               # ends at odd, odd, even step counts
+        aa.step(k)
+        ab.step(k)
+        assert torch.equal(aa.populations(), ab.populations()), k
+    aa.close()
+    ab.close()
+
+
 @pytest.mark.parametrize("forcing", ["guo", "edm", "hcz"])
 def test_aa_equals_ab_bitwise_other_forcings(forcing):
     kw = c1_kw(n=16, forcing=forcing)

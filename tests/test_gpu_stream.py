@@ -65,6 +65,12 @@ def test_free_streaming_other_launch_shapes(n):
     check_free_streaming(n, 27, 19, "fp32", "aa", seed=n)
 
 
+@pytest.mark.parametrize("storage", ["fp16", "bf16"])
+def test_free_streaming_row_aligned_odd_step(storage):
+    # 2-byte storage at 128^3: blocks of two whole rows, the odd step row-aligned
+    check_free_streaming(128, 27, 19, storage, "aa", seed=128)
+
+
 @pytest.mark.parametrize("n,storage", [(320, "fp32"), (512, "fp16"), (512, "bf16")])
 def test_free_streaming_sampled_large(n, storage):
     # 320^3: rows split over 5 blocks, XCD-ordered odd step; 512^3 2-byte storage: the
