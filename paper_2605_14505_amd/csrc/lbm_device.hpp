@@ -16,6 +16,7 @@
 // order.  MODE_AB is a two-lattice push variant (read natural at x, write
 // natural at x + e_i into a second array) kept for bitwise cross-checking.
 #pragma once
+#include <type_traits>
 #include <utility>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -187,28 +188,6 @@ __device__ __forceinline__ void gather(C* v, const T* pop, int first, const Node
   gather_seq<Q, T, MODE, NTX>(v, pop, first, ix, stride, std::make_integer_sequence<int, Q>{});
 }
 
-// The same gather as a loop over directions with cached loads, for the LDS-staged odd step:
-// there the compiler's schedule of this form is the faster one (512^3 FP16 odd step
-// 5.45 -> 5.25 ms on gfx950).
-template <int Q, typename T, int MODE, typename C>
-__device__ __forceinline__ void gather_loop(C* v, const T* pop, int first, const NodeIndex& ix,
-                                            int64_t stride) {
-  using S = Stencil<Q>;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    uint32_t off;
-    int slot;
-    if (MODE == MODE_ODD) {
-      off = ix.at(-S::ex[i], -S::ey[i], -S::ez[i]);
-      slot = opp(i);
-    } else {
-      off = ix.base;
-      slot = i;
-    }
-    v[i] = load_as<C>(at_node(pop + (int64_t)(first + slot) * stride, off));
-  }
-}
-
 // Scatter post-collision populations for MODE (AB writes into `dst`), one compile-time
 // direction at a time like gather.
 template <int Q, typename T, int MODE, int I, typename C>
@@ -233,18 +212,7 @@ __device__ __forceinline__ void scatter(const C* v, T* dst, int first, const Nod
 }
 
 // ---------------------------------------------------------------------------
-// x-staged push of the odd step (2-byte storage, blocks that hold part of a row)
-//
-// The odd step's push along e_x = +-1 moves a wavefront's 64 consecutive values
-// one element sideways, so each of its stores straddles a line boundary and
-// every line is completed by two wavefronts.  Staged, each lane first leaves
-// its rounded values of the directions with e_x != 0 in LDS at its own place
-// in the block; after one barrier lane x stores, at its own x, what lane
-// x - e_x left there, so the stores of a wavefront cover whole aligned lines.
-// The lanes at the block's x edges store their own value across the edge
-// directly, and the lane whose source sits in the neighbouring block stores
-// nothing for that direction: every destination is written exactly once, and
-// every location is still written after the barrier that follows its read.
+// Helpers of the row-aligned odd step
 // ---------------------------------------------------------------------------
 template <int Q>
 constexpr int x_moving() {
@@ -260,69 +228,24 @@ __device__ __forceinline__ bf16_t rounded(const bf16_t*, float v) {
 __device__ __forceinline__ void put_rounded(_Float16* p, _Float16 v) { put(p, v); }
 __device__ __forceinline__ void put_rounded(bf16_t* p, bf16_t v) { put(&p->bits, v.bits); }
 
-struct XLane {
-  int lid;           // thread index in the block (row-major over x, y)
-  int from_m;        // LDS place of the x - 1 neighbour (the lane's own at the block's left edge)
-  int from_p;        // ... of the x + 1 neighbour (own at the right edge)
-  bool left;         // first lane of its block row
-  bool right;        // last lane of its block row
-};
-
-__device__ __forceinline__ XLane make_xlane() {
-  const int tx = threadIdx.x, bx = blockDim.x;
-  XLane l;
-  l.left = tx == 0;
-  l.right = tx == bx - 1;
-  l.lid = threadIdx.y * bx + tx;
-  l.from_m = l.left ? l.lid : l.lid - 1;
-  l.from_p = l.right ? l.lid : l.lid + 1;
-  return l;
-}
-
-// Leave the rounded values of the directions with e_x != 0 in xs[k][lid].
-template <int Q, typename T, typename C>
-__device__ __forceinline__ void stage_x(const C* v, T (*xs)[256], int k0, const XLane& l) {
-  using S = Stencil<Q>;
-  int k = k0;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    if (S::ex[i] == 0) continue;
-    xs[k++][l.lid] = rounded((const T*)nullptr, v[i]);
-  }
-}
-
-// The odd step's push (slot i at x + e_i) with the x-shift taken from LDS.
-template <int Q, typename T, typename C>
-__device__ __forceinline__ void scatter_staged(const C* v, T* dst, int first, const NodeIndex& ix,
-                                               int64_t stride, const T (*xs)[256], int k0,
-                                               const XLane& l) {
-  using S = Stencil<Q>;
-  int k = k0;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    T* arr = dst + (int64_t)(first + i) * stride;
-    if (S::ex[i] == 0) {
-      store_as(at_node(arr, ix.at(0, S::ey[i], S::ez[i])), v[i]);
-      continue;
-    }
-    const bool plus = S::ex[i] > 0;
-    const T got = xs[k++][plus ? l.from_m : l.from_p];
-    if (!(plus ? l.left : l.right)) put_rounded(at_node(arr, ix.at(0, S::ey[i], S::ez[i])), got);
-    if (plus ? l.right : l.left) store_as(at_node(arr, ix.at(S::ex[i], S::ey[i], S::ez[i])), v[i]);
-  }
-}
-
 // ---------------------------------------------------------------------------
-// Row-aligned odd step (blocks of whole rows)
+// Row-aligned odd step
 //
-// Where a block holds whole rows of the box (its x extent is n), the odd step's
-// x-shift of +-1 never leaves the block.  Every lane then loads and stores only at its
-// own x: the values of the directions with e_x != 0 are loaded at x from the row of
-// (y - e_y, z - e_z) and left in LDS, and after a barrier lane x takes what lane
-// x - e_x of its row loaded (wrapped within the row); the post-collision values go the
-// other way, lane x leaving its value at x + e_x and storing, after a barrier, what was
-// left at its own place.  All global accesses are whole aligned lines and no line is
-// shared between wavefronts, so every load bypasses the caches.
+// The odd step's x-shift of +-1 taken through LDS.  For each direction with e_x != 0 the
+// lanes of a block row treat their LDS row as a ring of bx places: lane t loads at its
+// own x from the row of (y - e_y, z - e_z) and leaves the value at place t; after a
+// barrier it takes the value at place t - e_x (mod bx), i.e. that of node x - e_x.  The
+// post-collision values go the other way: lane t leaves its value at place t + e_x and,
+// after a barrier, stores what sits at place t at its own x.  Where a block holds whole
+// rows (bx = n) the ring is the row itself.  Where it holds part of a row, the ring's
+// seam is the block's edge: the lane whose own value no lane of the block needs (the
+// last lane for e_x = +1, the first for e_x = -1) loads instead the node across the
+// edge, x -+ bx, which its ring neighbour needs; and the lane whose place receives the
+// value that belongs across the edge stores it there, at x +- bx.  Every lane does one
+// load and one store per direction, every destination is written once, and the node
+// that reads a location before the step is the one that writes it, as in the plain AA
+// step.  All accesses are whole aligned lines except the two seam lanes', and bypass the
+// caches.
 // ---------------------------------------------------------------------------
 template <int Q>
 constexpr int x_slot(int i) {     // index of direction i among those with e_x != 0
@@ -333,50 +256,78 @@ constexpr int x_slot(int i) {     // index of direction i among those with e_x !
 
 __device__ __forceinline__ float rounded(const float*, float v) { return v; }
 __device__ __forceinline__ void put_rounded(float* p, float v) { put(p, v); }
-__device__ __forceinline__ float raw_load_nt(const float* p) { return get<true>(p); }
-__device__ __forceinline__ _Float16 raw_load_nt(const _Float16* p) { return get<true>(p); }
-__device__ __forceinline__ bf16_t raw_load_nt(const bf16_t* p) { return bf16_t{get<true>(&p->bits)}; }
+template <bool NT> __device__ __forceinline__ float raw_load(const float* p) { return get<NT>(p); }
+template <bool NT> __device__ __forceinline__ _Float16 raw_load(const _Float16* p) { return get<NT>(p); }
+template <bool NT> __device__ __forceinline__ bf16_t raw_load(const bf16_t* p) { return bf16_t{get<NT>(&p->bits)}; }
+template <bool NT, typename T> __device__ __forceinline__ void raw_store(T* p, T v) {
+  if constexpr (NT) put_rounded(p, v);
+  else if constexpr (sizeof(T) == 4) *p = v;
+  else if constexpr (std::is_same_v<T, bf16_t>) p->bits = v.bits;
+  else *p = v;
+}
 
 struct RowLane {
-  int lid;      // thread index in the block, = row * n + x
-  int row0;     // lid - x: the start of the lane's row in the block
-  int xm, xp;   // x - 1 and x + 1, wrapped within the row
+  int lid;          // thread index in the block
+  int place_m;      // ring place t - 1 (mod bx) in the block's LDS rows
+  int place_p;      // ring place t + 1 (mod bx)
+  uint32_t x_own;   // the lane's node x
+  uint32_t x_a;     // x + bx (mod n) for the first lane of the row, else x
+  uint32_t x_b;     // x - bx (mod n) for the last lane of the row, else x
 };
 
-template <int Q, typename T, int I, typename C>
+__device__ __forceinline__ RowLane make_rowlane(int x, int n) {
+  const int tx = threadIdx.x, bx = blockDim.x;
+  RowLane l;
+  l.lid = threadIdx.y * bx + tx;
+  const int row0 = l.lid - tx;
+  l.place_m = row0 + (tx == 0 ? bx - 1 : tx - 1);
+  l.place_p = row0 + (tx == bx - 1 ? 0 : tx + 1);
+  l.x_own = (uint32_t)x;
+  l.x_a = (uint32_t)(tx == 0 ? (x + bx) % n : x);
+  l.x_b = (uint32_t)(tx == bx - 1 ? (x - bx + n) % n : x);
+  return l;
+}
+
+template <int Q, typename T, bool NTX, int I, typename C>
 __device__ __forceinline__ void row_load_one(C* v, T (*xs)[256], int k0, const T* pop, int first,
                                              const NodeIndex& ix, int64_t stride, const RowLane& l) {
   using S = Stencil<Q>;
-  const T* p = at_node(pop + (int64_t)(first + opp(I)) * stride, ix.at(0, -S::ey[I], -S::ez[I]));
-  if constexpr (S::ex[I] == 0) v[I] = load_as<C, true>(p);
-  else xs[k0 + x_slot<Q>(I)][l.lid] = raw_load_nt(p);
+  constexpr int ex = S::ex[I];
+  // the ring's seam lane for e_x = +1 is the last, for e_x = -1 the first
+  const uint32_t xl = ex > 0 ? l.x_b : (ex < 0 ? l.x_a : l.x_own);
+  const T* p = at_node(pop + (int64_t)(first + opp(I)) * stride, xl + ix.yo[1 - S::ey[I]] + ix.zo[1 - S::ez[I]]);
+  if constexpr (ex == 0) v[I] = load_as<C, true>(p);
+  else xs[k0 + x_slot<Q>(I)][l.lid] = raw_load<NTX>(p);
 }
 template <int Q, typename T, int I, typename C>
 __device__ __forceinline__ void row_pick_one(C* v, const T (*xs)[256], int k0, const RowLane& l) {
   using S = Stencil<Q>;
-  if constexpr (S::ex[I] != 0)
-    v[I] = load_as<C>(&xs[k0 + x_slot<Q>(I)][l.row0 + (S::ex[I] > 0 ? l.xm : l.xp)]);
+  if constexpr (S::ex[I] != 0) v[I] = load_as<C>(&xs[k0 + x_slot<Q>(I)][S::ex[I] > 0 ? l.place_m : l.place_p]);
 }
 template <int Q, typename T, int I, typename C>
 __device__ __forceinline__ void row_put_one(const C* v, T (*xs)[256], int k0, const RowLane& l) {
   using S = Stencil<Q>;
   if constexpr (S::ex[I] != 0)
-    xs[k0 + x_slot<Q>(I)][l.row0 + (S::ex[I] > 0 ? l.xp : l.xm)] = rounded((const T*)nullptr, v[I]);
+    xs[k0 + x_slot<Q>(I)][S::ex[I] > 0 ? l.place_p : l.place_m] = rounded((const T*)nullptr, v[I]);
 }
-template <int Q, typename T, int I, typename C>
+template <int Q, typename T, bool NTX, int I, typename C>
 __device__ __forceinline__ void row_store_one(const C* v, const T (*xs)[256], int k0, T* dst, int first,
                                               const NodeIndex& ix, int64_t stride, const RowLane& l) {
   using S = Stencil<Q>;
-  T* p = at_node(dst + (int64_t)(first + I) * stride, ix.at(0, S::ey[I], S::ez[I]));
-  if constexpr (S::ex[I] == 0) store_as(p, v[I]);
-  else put_rounded(p, xs[k0 + x_slot<Q>(I)][l.lid]);
+  constexpr int ex = S::ex[I];
+  // the place that receives the value belonging across the seam: the first lane's for
+  // e_x = +1, the last lane's for e_x = -1
+  const uint32_t xd = ex > 0 ? l.x_a : (ex < 0 ? l.x_b : l.x_own);
+  T* p = at_node(dst + (int64_t)(first + I) * stride, xd + ix.yo[1 + S::ey[I]] + ix.zo[1 + S::ez[I]]);
+  if constexpr (ex == 0) store_as(p, v[I]);
+  else raw_store<NTX>(p, xs[k0 + x_slot<Q>(I)][l.lid]);
 }
 
-template <int Q, typename T, typename C, int... I>
+template <int Q, typename T, bool NTX, typename C, int... I>
 __device__ __forceinline__ void row_load(C* v, T (*xs)[256], int k0, const T* pop, int first,
                                          const NodeIndex& ix, int64_t stride, const RowLane& l,
                                          std::integer_sequence<int, I...>) {
-  (row_load_one<Q, T, I>(v, xs, k0, pop, first, ix, stride, l), ...);
+  (row_load_one<Q, T, NTX, I>(v, xs, k0, pop, first, ix, stride, l), ...);
 }
 template <int Q, typename T, typename C, int... I>
 __device__ __forceinline__ void row_pick(C* v, const T (*xs)[256], int k0, const RowLane& l,
@@ -388,11 +339,11 @@ __device__ __forceinline__ void row_put(const C* v, T (*xs)[256], int k0, const 
                                         std::integer_sequence<int, I...>) {
   (row_put_one<Q, T, I>(v, xs, k0, l), ...);
 }
-template <int Q, typename T, typename C, int... I>
+template <int Q, typename T, bool NTX, typename C, int... I>
 __device__ __forceinline__ void row_store(const C* v, const T (*xs)[256], int k0, T* dst, int first,
                                           const NodeIndex& ix, int64_t stride, const RowLane& l,
                                           std::integer_sequence<int, I...>) {
-  (row_store_one<Q, T, I>(v, xs, k0, dst, first, ix, stride, l), ...);
+  (row_store_one<Q, T, NTX, I>(v, xs, k0, dst, first, ix, stride, l), ...);
 }
 
 // ---------------------------------------------------------------------------

@@ -30,14 +30,13 @@ hipError_t step_force(int mode, bool diag, const LaunchShape& sh, hipStream_t st
               : go_step<QF, QG, FORCE, T, M, STEP>(sh, st, pop, dst, geo, c, fields, partials)
   if (mode == MODE_EVEN) STGV_GO(MODE_EVEN);
   if constexpr (sizeof(T) == 2) {
-    if (mode == MODE_ODD && !diag && rowshift_shape(sh, geo.n)) {
-      hipLaunchKernelGGL((lbm_step_rowshift_kernel<QF, QG, FORCE, T, STGV_C>), sh.grid, sh.block, 0, st,
-                         pop, geo, c);
-      return hipGetLastError();
-    }
-    if (mode == MODE_ODD && !diag && xstaged_shape(sh, geo.n)) {
-      hipLaunchKernelGGL((lbm_step_xstaged_kernel<QF, QG, FORCE, T, STGV_C>), sh.grid, sh.block, 0, st,
-                         pop, geo, c);
+    if (mode == MODE_ODD && !diag && ring_shape(sh, geo.n)) {
+      if (ring_whole_shape(sh, geo.n))
+        hipLaunchKernelGGL((lbm_step_ring_kernel<QF, QG, FORCE, T, STGV_C, false>), sh.grid, sh.block, 0, st,
+                           pop, geo, c);
+      else
+        hipLaunchKernelGGL((lbm_step_ring_kernel<QF, QG, FORCE, T, STGV_C, true>), sh.grid, sh.block, 0, st,
+                           pop, geo, c);
       return hipGetLastError();
     }
   }
@@ -109,17 +108,13 @@ hipError_t launch_init<STGV_T>(int qf, int qg, const LaunchShape& sh, hipStream_
 template <>
 hipError_t launch_stream<STGV_T>(int qf, int qg, int mode, const LaunchShape& sh, hipStream_t st,
                                  STGV_T* pop, STGV_T* dst, Geometry geo) {
-  const bool two = sizeof(STGV_T) == 2 && mode == MODE_ODD;
-  const bool rows = two && rowshift_shape(sh, geo.n);
-  const bool staged = two && !rows && xstaged_shape(sh, geo.n);
+  const bool ring = sizeof(STGV_T) == 2 && mode == MODE_ODD && ring_shape(sh, geo.n);
 #define STGV_STREAM(A, B) \
   if (qf == A && qg == B) { \
-    if (rows) { \
+    if (ring) { \
       if constexpr (sizeof(STGV_T) == 2) \
-        hipLaunchKernelGGL((lbm_stream_rowshift_kernel<A, B, STGV_T>), sh.grid, sh.block, 0, st, pop, geo); \
-    } else if (staged) { \
-      if constexpr (sizeof(STGV_T) == 2) \
-        hipLaunchKernelGGL((lbm_stream_xstaged_kernel<A, B, STGV_T>), sh.grid, sh.block, 0, st, pop, geo); \
+        { if (ring_whole_shape(sh, geo.n)) hipLaunchKernelGGL((lbm_stream_ring_kernel<A, B, STGV_T, false>), sh.grid, sh.block, 0, st, pop, geo); \
+          else hipLaunchKernelGGL((lbm_stream_ring_kernel<A, B, STGV_T, true>), sh.grid, sh.block, 0, st, pop, geo); } \
     } else if (mode == MODE_EVEN) hipLaunchKernelGGL((lbm_stream_kernel<A, B, STGV_T, MODE_EVEN>), sh.grid, sh.block, 0, st, pop, dst, geo); \
     else if (mode == MODE_ODD) hipLaunchKernelGGL((lbm_stream_kernel<A, B, STGV_T, MODE_ODD>), sh.grid, sh.block, 0, st, pop, dst, geo); \
     else if (mode == MODE_AB) hipLaunchKernelGGL((lbm_stream_kernel<A, B, STGV_T, MODE_AB>), sh.grid, sh.block, 0, st, pop, dst, geo); \

@@ -96,11 +96,26 @@ __global__ STGV_STEP_BOUNDS_FOR(MODE, FLAGS, T, C) void lbm_step_kernel(T* pop, 
   }
 }
 
-// The plain odd step with its x-shifted stores staged through LDS (scatter_staged).
-// Launched only for 2-byte storage on block shapes that tile the box exactly and
-// hold part of a row, so every lane is active and reaches the barrier.
-template <int QF, int QG, int FORCE, typename T, typename C>
-__global__ STGV_STEP_BOUNDS void lbm_step_xstaged_kernel(T* pop, Geometry geo, PhysConsts c) {
+// The plain odd step row-aligned, its x-shift taken through a ring in LDS per block row
+// (row_load / row_pick / row_put / row_store), on the shapes of ring_shape (blocks of
+// whole rows, or 256-node blocks holding part of one row), which tile the box exactly,
+// so every lane is active and reaches the barriers.
+// PART: blocks holding part of a row, whose x-moving loads and stores use the cache
+// policy STGV_RING_PART_NT_XLOAD / STGV_RING_PART_NT_XSTORE (1 = bypass); whole-row
+// blocks bypass the caches for every access.  A seam lane's load shares its line with
+// the neighbouring block's aligned load, which finds it in L2 only if it was loaded
+// cached: 512^3 odd step FP16 5.21 -> 4.80 ms, BF16 5.67 -> 4.82 ms with cached x-moving
+// loads; cached x-moving stores changed nothing further (4.80 / 4.80) and alone gave
+// 4.90 / 4.96.
+#ifndef STGV_RING_PART_NT_XLOAD
+#define STGV_RING_PART_NT_XLOAD 0
+#endif
+#ifndef STGV_RING_PART_NT_XSTORE
+#define STGV_RING_PART_NT_XSTORE 1
+#endif
+template <int QF, int QG, int FORCE, typename T, typename C, bool PART>
+__global__ STGV_STEP_BOUNDS void lbm_step_ring_kernel(T* pop, Geometry geo, PhysConsts c) {
+  constexpr bool NL = !PART || STGV_RING_PART_NT_XLOAD, NS = !PART || STGV_RING_PART_NT_XSTORE;
   constexpr int KF = x_moving<QF>(), KG = x_moving<QG>();
   __shared__ T xs[KF + KG][256];
   const int n = geo.n;
@@ -108,40 +123,10 @@ __global__ STGV_STEP_BOUNDS void lbm_step_xstaged_kernel(T* pop, Geometry geo, P
   const int x = blk.bx * blockDim.x + threadIdx.x;
   const int y = blk.by * blockDim.y + threadIdx.y;
   const NodeIndex ix = make_index(x, y, blk.bz, n);
+  const RowLane l = make_rowlane(x, n);
   C f[QF], g[QG];
-  gather_loop<QF, T, MODE_ODD>(f, pop, 0, ix, geo.stride);
-  gather_loop<QG, T, MODE_ODD>(g, pop, QF, ix, geo.stride);
-  StepMacro<C> m;
-  step_macro<QF, QG, FORCE, sizeof(T) == 4>(f, g, c, m);
-  step_collide<QF, QG, FORCE, sizeof(T) == 4>(f, g, c, m);
-  const XLane l = make_xlane();
-  stage_x<QF>(f, xs, 0, l);
-  stage_x<QG>(g, xs, KF, l);
-  __syncthreads();
-  scatter_staged<QF>(f, pop, 0, ix, geo.stride, xs, 0, l);
-  scatter_staged<QG>(g, pop, QF, ix, geo.stride, xs, KF, l);
-}
-
-// The plain odd step on blocks of whole rows, all loads and stores row-aligned with the
-// x-shift taken through LDS (row_load / row_pick / row_put / row_store).  Launched only on
-// shapes whose blocks hold whole rows and tile the box exactly (rowshift_shape), so every
-// lane is active and reaches the barriers.
-template <int QF, int QG, int FORCE, typename T, typename C>
-__global__ STGV_STEP_BOUNDS void lbm_step_rowshift_kernel(T* pop, Geometry geo, PhysConsts c) {
-  constexpr int KF = x_moving<QF>(), KG = x_moving<QG>();
-  __shared__ T xs[KF + KG][256];
-  const int n = geo.n;
-  const int x = threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  const NodeIndex ix = make_index(x, y, blockIdx.z, n);
-  RowLane l;
-  l.lid = threadIdx.y * blockDim.x + x;
-  l.row0 = l.lid - x;
-  l.xm = (int)ix.xo[0];
-  l.xp = (int)ix.xo[2];
-  C f[QF], g[QG];
-  row_load<QF>(f, xs, 0, pop, 0, ix, geo.stride, l, std::make_integer_sequence<int, QF>{});
-  row_load<QG>(g, xs, KF, pop, QF, ix, geo.stride, l, std::make_integer_sequence<int, QG>{});
+  row_load<QF, T, NL>(f, xs, 0, pop, 0, ix, geo.stride, l, std::make_integer_sequence<int, QF>{});
+  row_load<QG, T, NL>(g, xs, KF, pop, QF, ix, geo.stride, l, std::make_integer_sequence<int, QG>{});
   __syncthreads();
   row_pick<QF>(f, (const T(*)[256])xs, 0, l, std::make_integer_sequence<int, QF>{});
   row_pick<QG>(g, (const T(*)[256])xs, KF, l, std::make_integer_sequence<int, QG>{});
@@ -152,8 +137,8 @@ __global__ STGV_STEP_BOUNDS void lbm_step_rowshift_kernel(T* pop, Geometry geo, 
   row_put<QF>(f, xs, 0, l, std::make_integer_sequence<int, QF>{});
   row_put<QG>(g, xs, KF, l, std::make_integer_sequence<int, QG>{});
   __syncthreads();
-  row_store<QF>(f, (const T(*)[256])xs, 0, pop, 0, ix, geo.stride, l, std::make_integer_sequence<int, QF>{});
-  row_store<QG>(g, (const T(*)[256])xs, KF, pop, QF, ix, geo.stride, l, std::make_integer_sequence<int, QG>{});
+  row_store<QF, T, NS>(f, (const T(*)[256])xs, 0, pop, 0, ix, geo.stride, l, std::make_integer_sequence<int, QF>{});
+  row_store<QG, T, NS>(g, (const T(*)[256])xs, KF, pop, QF, ix, geo.stride, l, std::make_integer_sequence<int, QG>{});
 }
 
 // ---------------------------------------------------------------------------
@@ -179,37 +164,10 @@ __global__ __launch_bounds__(256) void lbm_stream_kernel(T* pop, T* dst, Geometr
 }
 
 // The odd free-streaming step row-aligned, on the shapes where the odd step of 2-byte
-// storage runs row-aligned (every lane active).
-template <int QF, int QG, typename T>
-__global__ __launch_bounds__(256) void lbm_stream_rowshift_kernel(T* pop, Geometry geo) {
-  constexpr int KF = x_moving<QF>(), KG = x_moving<QG>();
-  __shared__ T xs[KF + KG][256];
-  const int n = geo.n;
-  const int x = threadIdx.x;
-  const NodeIndex ix = make_index(x, blockIdx.y * blockDim.y + threadIdx.y, blockIdx.z, n);
-  RowLane l;
-  l.lid = threadIdx.y * blockDim.x + x;
-  l.row0 = l.lid - x;
-  l.xm = (int)ix.xo[0];
-  l.xp = (int)ix.xo[2];
-  float f[QF], g[QG];
-  row_load<QF>(f, xs, 0, pop, 0, ix, geo.stride, l, std::make_integer_sequence<int, QF>{});
-  row_load<QG>(g, xs, KF, pop, QF, ix, geo.stride, l, std::make_integer_sequence<int, QG>{});
-  __syncthreads();
-  row_pick<QF>(f, (const T(*)[256])xs, 0, l, std::make_integer_sequence<int, QF>{});
-  row_pick<QG>(g, (const T(*)[256])xs, KF, l, std::make_integer_sequence<int, QG>{});
-  __syncthreads();
-  row_put<QF>(f, xs, 0, l, std::make_integer_sequence<int, QF>{});
-  row_put<QG>(g, xs, KF, l, std::make_integer_sequence<int, QG>{});
-  __syncthreads();
-  row_store<QF>(f, (const T(*)[256])xs, 0, pop, 0, ix, geo.stride, l, std::make_integer_sequence<int, QF>{});
-  row_store<QG>(g, (const T(*)[256])xs, KF, pop, QF, ix, geo.stride, l, std::make_integer_sequence<int, QG>{});
-}
-
-// The odd free-streaming step with the x-shifted stores staged through LDS, on the
-// launch shapes where the odd step of 2-byte storage is staged (every lane active).
-template <int QF, int QG, typename T>
-__global__ __launch_bounds__(256) void lbm_stream_xstaged_kernel(T* pop, Geometry geo) {
+// storage runs row-aligned (ring_shape; every lane active).
+template <int QF, int QG, typename T, bool PART>
+__global__ __launch_bounds__(256) void lbm_stream_ring_kernel(T* pop, Geometry geo) {
+  constexpr bool NL = !PART || STGV_RING_PART_NT_XLOAD, NS = !PART || STGV_RING_PART_NT_XSTORE;
   constexpr int KF = x_moving<QF>(), KG = x_moving<QG>();
   __shared__ T xs[KF + KG][256];
   const int n = geo.n;
@@ -217,15 +175,19 @@ __global__ __launch_bounds__(256) void lbm_stream_xstaged_kernel(T* pop, Geometr
   const int x = blk.bx * blockDim.x + threadIdx.x;
   const int y = blk.by * blockDim.y + threadIdx.y;
   const NodeIndex ix = make_index(x, y, blk.bz, n);
+  const RowLane l = make_rowlane(x, n);
   float f[QF], g[QG];
-  gather_loop<QF, T, MODE_ODD>(f, pop, 0, ix, geo.stride);
-  gather_loop<QG, T, MODE_ODD>(g, pop, QF, ix, geo.stride);
-  const XLane l = make_xlane();
-  stage_x<QF>(f, xs, 0, l);
-  stage_x<QG>(g, xs, KF, l);
+  row_load<QF, T, NL>(f, xs, 0, pop, 0, ix, geo.stride, l, std::make_integer_sequence<int, QF>{});
+  row_load<QG, T, NL>(g, xs, KF, pop, QF, ix, geo.stride, l, std::make_integer_sequence<int, QG>{});
   __syncthreads();
-  scatter_staged<QF>(f, pop, 0, ix, geo.stride, xs, 0, l);
-  scatter_staged<QG>(g, pop, QF, ix, geo.stride, xs, KF, l);
+  row_pick<QF>(f, (const T(*)[256])xs, 0, l, std::make_integer_sequence<int, QF>{});
+  row_pick<QG>(g, (const T(*)[256])xs, KF, l, std::make_integer_sequence<int, QG>{});
+  __syncthreads();
+  row_put<QF>(f, xs, 0, l, std::make_integer_sequence<int, QF>{});
+  row_put<QG>(g, xs, KF, l, std::make_integer_sequence<int, QG>{});
+  __syncthreads();
+  row_store<QF, T, NS>(f, (const T(*)[256])xs, 0, pop, 0, ix, geo.stride, l, std::make_integer_sequence<int, QF>{});
+  row_store<QG, T, NS>(g, (const T(*)[256])xs, KF, pop, QF, ix, geo.stride, l, std::make_integer_sequence<int, QG>{});
 }
 
 // ---------------------------------------------------------------------------

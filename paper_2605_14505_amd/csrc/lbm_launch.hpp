@@ -44,33 +44,22 @@ inline LaunchShape node_shape(int n) {
   return s;
 }
 
-// Whether the odd step of 2-byte storage stages its x-shifted stores through LDS
-// (lbm_step_xstaged_kernel): where 256-node blocks tile the box exactly and hold
-// part of a row, on boxes of at least STGV_XSTAGE_MIN_N a side.  Measured on
-// gfx950 (FP16 / BF16 odd step): 512^3 6.50 -> 5.77 ms and 6.41 -> 5.84 ms; with
-// 64- or 128-node blocks (320^3 - 448^3) and with whole rows in a block (256^3)
-// staging was slower, so those keep the plain push.
-#ifndef STGV_XSTAGE_MIN_N
-#define STGV_XSTAGE_MIN_N 512
-#endif
-inline bool xstaged_shape(const LaunchShape& sh, int n) {
+// Whether the plain odd step of 2-byte storage runs row-aligned through an LDS ring
+// (lbm_step_ring_kernel): on blocks of whole rows that tile the box (n = 128, 256) or on
+// 256-node blocks holding part of one row (n a multiple of 256, from 512).  Measured on
+// gfx950 (D3Q27 x D3Q19 odd step, against the shifted loads and stores): 256^3 FP16
+// 0.566 -> 0.543 ms, BF16 0.573 -> 0.538 ms, 128^3 -1.6 % over the mean step; 512^3 FP16
+// 4.80 ms and BF16 4.82 ms against 5.22 and 9.5 for LDS-staged stores alone.  FP32
+// storage gained nothing at 256^3 and lost at 128^3 and 64^3, so it keeps the shifted
+// accesses.
+inline bool ring_whole_shape(const LaunchShape& sh, int n) {
   const int bx = (int)sh.block.x, by = (int)sh.block.y;
-  return n >= STGV_XSTAGE_MIN_N && bx == 256 && by == 1 && n % bx == 0 && bx < n;
+  return n >= 128 && bx == n && sh.grid.x == 1 && bx * by == 256 && n % by == 0;
 }
-
-// Whether the plain odd step of 2-byte storage runs row-aligned
-// (lbm_step_rowshift_kernel): blocks of whole rows (x extent n, one block across x) that
-// tile the box exactly, n >= 128.  Measured on gfx950 (D3Q27 x D3Q19, odd step): 256^3
-// FP16 0.561 -> 0.532 ms, BF16 0.574 -> 0.529 ms, 128^3 FP16 -1.6 % over the mean step;
-// FP32 storage gained nothing at 256^3 and lost 13 % at 128^3 and 2.5 % at 64^3, so it
-// keeps the shifted loads and stores.
-#ifndef STGV_ROWSHIFT_MIN_N
-#define STGV_ROWSHIFT_MIN_N 128
-#endif
-inline bool rowshift_shape(const LaunchShape& sh, int n) {
-  const int bx = (int)sh.block.x, by = (int)sh.block.y;
-  return n >= STGV_ROWSHIFT_MIN_N && bx == n && sh.grid.x == 1 && bx * by == 256 && n % by == 0;
+inline bool ring_part_shape(const LaunchShape& sh, int n) {
+  return n >= 512 && sh.block.x == 256 && sh.block.y == 1 && n % 256 == 0;
 }
+inline bool ring_shape(const LaunchShape& sh, int n) { return ring_whole_shape(sh, n) || ring_part_shape(sh, n); }
 
 // Every function returns the launch error (hipSuccess when queued).
 template <typename T, typename C>

@@ -68,13 +68,13 @@ def counter_means(pmc_dir):
 
 
 def is_step_kernel(name):
-    return "lbm_step_kernel" in name or "lbm_step_xstaged_kernel" in name
+    return "lbm_step_kernel" in name or "lbm_step_ring_kernel" in name
 
 
 def is_plain_step(name):
     """A time step without diagnostic outputs: FLAGS == 1 (the last template argument, in
-    the demangled or the mangled name), or the LDS-staged odd step, which has no flags."""
-    if "lbm_step_xstaged_kernel" in name:
+    the demangled or the mangled name), or the row-aligned odd step, which has no flags."""
+    if "lbm_step_ring_kernel" in name:
         return True
     m = re.search(r"lbm_step_kernel<[^>]*, (\d+)>\(", name) or re.search(r"lbm_step_kernelI.*ELi(\d+)EEEv", name)
     return bool(m) and m.group(1) == "1"

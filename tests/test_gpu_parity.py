@@ -476,8 +476,8 @@ def test_large_512_fp16_sampled_parity():
     # velocity shift, Re 3200, Fr 0.5.  Against the FP64 oracle the error is FP16 storage
     # rounding: one rounding of the initial deviations and one per step, each at most
     # 2^-11 of a deviation, so 3 * 2^-11 of the largest deviation after one step.
-    # Each further step adds at most one more rounding; step 2 is an odd step, whose
-    # x-shifted stores go through LDS at this size (lbm_step_xstaged_kernel).
+    # Each further step adds at most one more rounding; step 2 is an odd step, which at
+    # this size runs row-aligned, its x-shift through an LDS ring (lbm_step_ring_kernel).
     kw = dict(n=512, q_f=27, q_g=19, forcing="shift", storage="fp16", u0=0.05, re=3200.0, fr=0.5,
               sc=0.7, g_over_n=0.02, noise_amp=1e-6, seed=0)
     for steps in (1, 2):
@@ -485,10 +485,11 @@ def test_large_512_fp16_sampled_parity():
 
 
 @pytest.mark.parametrize("storage", ["fp16", "bf16"])
-def test_large_512_staged_odd_step_equals_ab_push(storage):
-    # At 512^3 the odd AA step of 2-byte storage stages its x-shifted stores through
-    # LDS; the A-B push does not.  Both store the same rounded values at the same
-    # places, so the states agree bit for bit after odd and even step counts.
+def test_large_512_ring_odd_step_equals_ab_push(storage):
+    # At 512^3 the odd AA step of 2-byte storage runs row-aligned, its x-shift through an
+    # LDS ring whose seam lanes reach across the block's edge; the A-B push does not.  Both
+    # store the same rounded values at the same places, so the states agree bit for bit
+    # after odd and even step counts.
     kw = dict(n=512, q_f=27, q_g=19, forcing="shift", storage=storage, u0=0.05, re=3200.0,
               fr=0.5, sc=0.7, g_over_n=0.02, noise_amp=1e-6, seed=0)
     aa = gpu_sim(layout="aa", **kw)
@@ -508,7 +509,7 @@ def test_maximum_box_1024_fp16_sampled_parity():
     # offsets at the top of their 32-bit range).  The state is read raw at sampled nodes
     # after two steps, when the AA layout is back in natural order (slot i at node x); the
     # samples include the box corners and the x-edges of the 256-node blocks, where the
-    # staged odd step stores across block edges.
+    # seam lanes of the row-aligned odd step load and store across block edges.
     torch.cuda.empty_cache()
     n, steps = 1024, 2
     kw = dict(n=n, q_f=27, q_g=19, forcing="shift", storage="fp16", u0=0.05, re=3200.0, fr=0.5,

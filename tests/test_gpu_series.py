@@ -42,9 +42,15 @@ def test_energy_and_dissipation_histories_match_the_oracle(compute):
     floor = _errors(GOLD["fp32_storage"], fp64)          # FP32 storage rounding alone
     err = _errors(_gpu_history(compute=compute), fp64)
     print(f"\n{compute} arithmetic, {GOLD['steps']} steps at 64^3: errors {err}\n  fp32-storage floor {floor}")
+    # Relative to each history's largest value.  The floor (the oracle with its populations
+    # rounded to FP32 after every step) is 1.4e-9 - 1.2e-8 here.  The kernels are
+    # deterministic, so these errors are the same bits on every run: FP64 arithmetic
+    # measures 1.7 - 2.3 x the floor (the storage rounding is its only error), FP32
+    # arithmetic 4 - 25 x (its collision rounds each population several more times per
+    # step, and near tau = 1/2 those roundings add up over the 2500 steps).
+    bar = 4.0 if compute == "fp64" else 40.0
     for k in KEYS:
-        # relative to each history's largest value; the storage floor is ~1e-9 - 1e-8 here
-        assert err[k] <= max(1e-6, 100.0 * floor[k]), (k, err[k], floor[k])
+        assert err[k] <= bar * floor[k], (k, err[k], floor[k], bar)
 
 
 @pytest.mark.parametrize("storage,bar", [("fp16", 2 * 2.0 ** -11), ("bf16", 8 * 2.0 ** -8)])

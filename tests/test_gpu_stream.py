@@ -74,7 +74,8 @@ def test_free_streaming_row_aligned_odd_step(storage):
 @pytest.mark.parametrize("n,storage", [(320, "fp32"), (512, "fp16"), (512, "bf16")])
 def test_free_streaming_sampled_large(n, storage):
     # 320^3: rows split over 5 blocks, XCD-ordered odd step; 512^3 2-byte storage: the
-    # LDS-staged odd step.  Two calls cover an even and an odd step.
+    # row-aligned odd step, whose seam lanes reach across block edges.  Two calls cover an
+    # even and an odd step.
     q_f, q_g = 27, 19
     print(f"\nfree streaming sampled n={n} {storage}", flush=True)
     sim = make_sim(n, q_f, q_g, storage)
