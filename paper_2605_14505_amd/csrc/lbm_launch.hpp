@@ -61,6 +61,29 @@ inline bool ring_part_shape(const LaunchShape& sh, int n) {
 }
 inline bool ring_shape(const LaunchShape& sh, int n) { return ring_whole_shape(sh, n) || ring_part_shape(sh, n); }
 
+// Blocks resident per CU for the plain even step (0 = as many as the registers allow), set
+// by requesting unused dynamic LDS (160 KiB per CU): FP32 storage for n >= 256, 2-byte
+// storage for n >= 512.  The even step keeps every population array of its resident
+// wavefronts open at once; past ~70-95 KB of loads in flight per CU more wavefronts only
+// add open streams.  Measured on gfx950 (D3Q27 x D3Q19 even step, ms): FP32 at 2 blocks
+// instead of 4, 256^3 1.137 -> 1.080, 384^3 4.02 -> 3.84, 512^3 9.26 -> 8.98 (3 blocks:
+// 1.131 at 256^3); 2-byte storage at 3 blocks instead of 4, 512^3 FP16 4.67 -> 4.42, BF16
+// 5.00 -> 4.92, while 256^3 and 128^3 lose with any cap.  The odd step, whose x-shifted
+// lines neighbouring wavefronts share, gains nothing from a cap.
+#ifndef STGV_EVEN_CAP_FP32
+#define STGV_EVEN_CAP_FP32 2
+#endif
+#ifndef STGV_EVEN_CAP_2B
+#define STGV_EVEN_CAP_2B 3
+#endif
+inline size_t even_step_lds(size_t elem, int n) {
+  const int cap = elem == 4 ? (n >= 256 ? STGV_EVEN_CAP_FP32 : 0) : (n >= 512 ? STGV_EVEN_CAP_2B : 0);
+  if (cap <= 0) return 0;
+  // just over a (cap + 1)-th of the CU's LDS, so that cap blocks fit and cap + 1 do not
+  size_t b = (160u * 1024u) / (size_t)(cap + 1) + 1024u;
+  return b > 65536u ? 65536u : b;
+}
+
 // Every function returns the launch error (hipSuccess when queued).
 template <typename T, typename C>
 hipError_t launch_step(int qf, int qg, int force, int mode, int flags, const LaunchShape& sh,
