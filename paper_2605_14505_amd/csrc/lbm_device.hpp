@@ -79,8 +79,8 @@ struct bf16_t { uint16_t bits; };
 // gfx950 (256^3 D3Q27 x D3Q19, FP32 / FP16 storage), non-temporal loads of the even step
 // and of the odd step's x-aligned directions take 7-8 % off both steps, while
 // non-temporal loads of the x-shifted directions, whose lines two wavefronts share, make
-// the odd step 20-30 % slower.  The odd step of 2-byte storage at 512^3, whose x-moving
-// stores go through LDS, is 4 % slower with them and keeps cached loads.
+// the odd step 20-30 % slower.  (The row-aligned odd step, lbm_step_ring_kernel, sets
+// its own cache policy.)
 #ifndef STGV_NT_LOAD_MODES
 #define STGV_NT_LOAD_MODES 1
 #endif

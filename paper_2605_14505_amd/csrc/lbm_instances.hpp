@@ -30,14 +30,15 @@ hipError_t step_force(int mode, bool diag, const LaunchShape& sh, hipStream_t st
   return diag ? go_step<QF, QG, FORCE, T, M, STEP_DIAG>(sh, st, pop, dst, geo, c, fields, partials) \
               : go_step<QF, QG, FORCE, T, M, STEP>(sh, st, pop, dst, geo, c, fields, partials)
   if (mode == MODE_EVEN) STGV_GO(MODE_EVEN);
-  if constexpr (sizeof(T) == 2) {
-    if (mode == MODE_ODD && !diag && ring_shape(sh, geo.n)) {
-      if (ring_whole_shape(sh, geo.n))
-        hipLaunchKernelGGL((lbm_step_ring_kernel<QF, QG, FORCE, T, STGV_C, false>), sh.grid, sh.block, 0, st,
-                           pop, geo, c);
+  if constexpr (sizeof(STGV_C) == 4 && ring_pair<QF, QG>(sizeof(T))) {
+    if (mode == MODE_ODD && !diag && ring_shape(sh, geo.n, sizeof(T))) {
+      const size_t lds = ring_step_lds(sizeof(T), (size_t)(x_moving<QF>() + x_moving<QG>()) * 256 * sizeof(T));
+      if (ring_whole_shape(sh, geo.n, sizeof(T)))
+        hipLaunchKernelGGL((lbm_step_ring_kernel<QF, QG, FORCE, T, STGV_C, false>), sh.grid, sh.block, lds,
+                           st, pop, geo, c);
       else
-        hipLaunchKernelGGL((lbm_step_ring_kernel<QF, QG, FORCE, T, STGV_C, true>), sh.grid, sh.block, 0, st,
-                           pop, geo, c);
+        hipLaunchKernelGGL((lbm_step_ring_kernel<QF, QG, FORCE, T, STGV_C, true>), sh.grid, sh.block, lds,
+                           st, pop, geo, c);
       return hipGetLastError();
     }
   }
@@ -109,14 +110,19 @@ hipError_t launch_init<STGV_T>(int qf, int qg, const LaunchShape& sh, hipStream_
 template <>
 hipError_t launch_stream<STGV_T>(int qf, int qg, int mode, const LaunchShape& sh, hipStream_t st,
                                  STGV_T* pop, STGV_T* dst, Geometry geo) {
-  const bool ring = sizeof(STGV_T) == 2 && mode == MODE_ODD && ring_shape(sh, geo.n);
+  const bool ring = mode == MODE_ODD && ring_shape(sh, geo.n, sizeof(STGV_T));
+  const bool whole = ring_whole_shape(sh, geo.n, sizeof(STGV_T));
 #define STGV_STREAM(A, B) \
   if (qf == A && qg == B) { \
-    if (ring) { \
-      if constexpr (sizeof(STGV_T) == 2) \
-        { if (ring_whole_shape(sh, geo.n)) hipLaunchKernelGGL((lbm_stream_ring_kernel<A, B, STGV_T, false>), sh.grid, sh.block, 0, st, pop, geo); \
-          else hipLaunchKernelGGL((lbm_stream_ring_kernel<A, B, STGV_T, true>), sh.grid, sh.block, 0, st, pop, geo); } \
-    } else if (mode == MODE_EVEN) hipLaunchKernelGGL((lbm_stream_kernel<A, B, STGV_T, MODE_EVEN>), sh.grid, sh.block, even_step_lds(sizeof(STGV_T), geo.n), st, pop, dst, geo); \
+    if constexpr (ring_pair<A, B>(sizeof(STGV_T))) { \
+      if (ring) { \
+        const size_t lds = ring_step_lds(sizeof(STGV_T), (size_t)(x_moving<A>() + x_moving<B>()) * 256 * sizeof(STGV_T)); \
+        if (whole) hipLaunchKernelGGL((lbm_stream_ring_kernel<A, B, STGV_T, false>), sh.grid, sh.block, lds, st, pop, geo); \
+        else hipLaunchKernelGGL((lbm_stream_ring_kernel<A, B, STGV_T, true>), sh.grid, sh.block, lds, st, pop, geo); \
+        return hipGetLastError(); \
+      } \
+    } \
+    if (mode == MODE_EVEN) hipLaunchKernelGGL((lbm_stream_kernel<A, B, STGV_T, MODE_EVEN>), sh.grid, sh.block, even_step_lds(sizeof(STGV_T), geo.n), st, pop, dst, geo); \
     else if (mode == MODE_ODD) hipLaunchKernelGGL((lbm_stream_kernel<A, B, STGV_T, MODE_ODD>), sh.grid, sh.block, 0, st, pop, dst, geo); \
     else if (mode == MODE_AB) hipLaunchKernelGGL((lbm_stream_kernel<A, B, STGV_T, MODE_AB>), sh.grid, sh.block, 0, st, pop, dst, geo); \
     else return hipErrorInvalidValue; \

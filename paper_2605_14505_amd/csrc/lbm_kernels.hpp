@@ -163,8 +163,8 @@ __global__ __launch_bounds__(256) void lbm_stream_kernel(T* pop, T* dst, Geometr
   scatter<QG, T, MODE>(g, dst, QF, ix, geo.stride);
 }
 
-// The odd free-streaming step row-aligned, on the shapes where the odd step of 2-byte
-// storage runs row-aligned (ring_shape; every lane active).
+// The odd free-streaming step row-aligned, on the shapes where the odd step runs
+// row-aligned (ring_shape; every lane active).
 template <int QF, int QG, typename T, bool PART>
 __global__ __launch_bounds__(256) void lbm_stream_ring_kernel(T* pop, Geometry geo) {
   constexpr bool NL = !PART || STGV_RING_PART_NT_XLOAD, NS = !PART || STGV_RING_PART_NT_XSTORE;

@@ -44,22 +44,31 @@ inline LaunchShape node_shape(int n) {
   return s;
 }
 
-// Whether the plain odd step of 2-byte storage runs row-aligned through an LDS ring
-// (lbm_step_ring_kernel): on blocks of whole rows that tile the box (n = 128, 256) or on
-// 256-node blocks holding part of one row (n a multiple of 256, from 512).  Measured on
-// gfx950 (D3Q27 x D3Q19 odd step, against the shifted loads and stores): 256^3 FP16
-// 0.566 -> 0.543 ms, BF16 0.573 -> 0.538 ms, 128^3 -1.6 % over the mean step; 512^3 FP16
-// 4.80 ms and BF16 4.82 ms against 5.22 and 9.5 for LDS-staged stores alone.  FP32
-// storage gained nothing at 256^3 and lost at 128^3 and 64^3, so it keeps the shifted
-// accesses.
-inline bool ring_whole_shape(const LaunchShape& sh, int n) {
+// Whether the plain odd step runs row-aligned through an LDS ring (lbm_step_ring_kernel):
+// on blocks of whole rows that tile the box or on 256-node blocks holding part of one
+// row (n a multiple of 256, from 512); whole rows from n = 128 for 2-byte storage, from
+// n = 256 for FP32 (FP32 at 128^3 and 64^3 lost 13 % and 2.5 % with it).  Only for the
+// stencil pairs where it measured faster (ring_pair).  Measured on gfx950 (odd step, ms,
+// shifted loads and stores -> ring): 256^3 FP32 27x19 1.141 -> 1.090 (2 blocks per CU,
+// ring_step_lds), 19x19 0.957 -> 0.871, 7x27 0.819 -> 0.805; FP16 27x19 0.567 -> 0.549,
+// 27x7 0.403 -> 0.396; 512^3 27x19 FP32 9.61 -> 9.22, FP16 4.80 and BF16 4.82 against 5.22
+// and 9.5 for LDS-staged stores alone.  Slower with the ring, so shifted: FP32 27x27
+// (1.377 -> 1.822), 19x15, 15x7, 19x7, 27x7 (within 1 %); FP16 19x7 (0.294 -> 0.308).
+template <int QF, int QG>
+constexpr bool ring_pair(size_t elem) {
+  return elem == 4 ? ((QF == 27 && QG == 19) || (QF == 19 && QG == 19) || (QF == 7 && QG == 27))
+                   : ((QF == 27 && QG == 19) || (QF == 27 && QG == 7));
+}
+inline bool ring_whole_shape(const LaunchShape& sh, int n, size_t elem) {
   const int bx = (int)sh.block.x, by = (int)sh.block.y;
-  return n >= 128 && bx == n && sh.grid.x == 1 && bx * by == 256 && n % by == 0;
+  return n >= (elem == 4 ? 256 : 128) && bx == n && sh.grid.x == 1 && bx * by == 256 && n % by == 0;
 }
 inline bool ring_part_shape(const LaunchShape& sh, int n) {
   return n >= 512 && sh.block.x == 256 && sh.block.y == 1 && n % 256 == 0;
 }
-inline bool ring_shape(const LaunchShape& sh, int n) { return ring_whole_shape(sh, n) || ring_part_shape(sh, n); }
+inline bool ring_shape(const LaunchShape& sh, int n, size_t elem) {
+  return ring_whole_shape(sh, n, elem) || ring_part_shape(sh, n);
+}
 
 // Blocks resident per CU for the plain even step (0 = as many as the registers allow), set
 // by requesting unused dynamic LDS (160 KiB per CU): FP32 storage for n >= 256, 2-byte
@@ -82,6 +91,24 @@ inline size_t even_step_lds(size_t elem, int n) {
   // just over a (cap + 1)-th of the CU's LDS, so that cap blocks fit and cap + 1 do not
   size_t b = (160u * 1024u) / (size_t)(cap + 1) + 1024u;
   return b > 65536u ? 65536u : b;
+}
+
+// Blocks resident per CU for the ring odd step (0 = as many as registers and its LDS
+// allow), counting the kernel's own LDS of `static_lds` bytes: FP32 at 2 (256^3 odd step
+// 1.103 -> 1.088 ms, 512^3 9.37 -> 9.22 against no cap); 2-byte storage lost with a cap
+// of 2 (256^3 0.553 -> 0.600) and keeps none.
+#ifndef STGV_ODD_CAP_FP32
+#define STGV_ODD_CAP_FP32 2
+#endif
+#ifndef STGV_ODD_CAP_2B
+#define STGV_ODD_CAP_2B 0
+#endif
+inline size_t ring_step_lds(size_t elem, size_t static_lds) {
+  const int cap = elem == 4 ? STGV_ODD_CAP_FP32 : STGV_ODD_CAP_2B;
+  if (cap <= 0) return 0;
+  const size_t want = (160u * 1024u) / (size_t)(cap + 1) + 1024u;
+  if (want <= static_lds) return 0;
+  return want > 65536u ? 65536u - static_lds : want - static_lds;
 }
 
 // Every function returns the launch error (hipSuccess when queued).

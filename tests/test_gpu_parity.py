@@ -268,12 +268,15 @@ def test_aa_equals_ab_bitwise(storage):
         assert torch.equal(aa.fields(), ab.fields()), n
 
 
-@pytest.mark.parametrize("storage,n", [("fp16", 128), ("bf16", 128), ("fp16", 256), ("bf16", 256)])
-def test_aa_equals_ab_bitwise_whole_row_blocks(storage, n):
-    # 2-byte storage on blocks of whole rows that tile the box: the odd AA step runs
-    # row-aligned, its x-shift taken through LDS; the A-B push does not, so equality pins
-    # it bit for bit
-    kw = c1_kw(n=n, forcing="shift", storage=storage, g_over_n=0.02)
+@pytest.mark.parametrize("storage,n,q_f,q_g", [("fp16", 128, 27, 19), ("bf16", 128, 27, 19),
+                                               ("fp16", 256, 27, 19), ("bf16", 256, 27, 19),
+                                               ("fp32", 256, 27, 19), ("fp16", 128, 27, 7),
+                                               ("fp32", 256, 19, 19), ("fp32", 256, 7, 27)])
+def test_aa_equals_ab_bitwise_whole_row_blocks(storage, n, q_f, q_g):
+    # blocks of whole rows that tile the box (2-byte storage from 128^3, FP32 from 256^3),
+    # for the stencil pairs whose odd AA step runs row-aligned, its x-shift taken through
+    # LDS; the A-B push does not, so equality pins it bit for bit
+    kw = c1_kw(n=n, q_f=q_f, q_g=q_g, forcing="shift", storage=storage, g_over_n=0.02)
     aa = gpu_sim(layout="aa", **kw)
     ab = gpu_sim(layout="ab", **kw)
     for k in (1, 2, 7):               # ends at odd, odd, even step counts
@@ -484,12 +487,13 @@ def test_large_512_fp16_sampled_parity():
         _sampled_patch_parity(kw, steps, 16, tol=(steps + 2) * 2.0 ** -11)
 
 
-@pytest.mark.parametrize("storage", ["fp16", "bf16"])
+@pytest.mark.parametrize("storage", ["fp16", "bf16", "fp32"])
 def test_large_512_ring_odd_step_equals_ab_push(storage):
-    # At 512^3 the odd AA step of 2-byte storage runs row-aligned, its x-shift through an
+    # At 512^3 the odd AA step runs row-aligned, its x-shift through an
     # LDS ring whose seam lanes reach across the block's edge; the A-B push does not.  Both
     # store the same rounded values at the same places, so the states agree bit for bit
     # after odd and even step counts.
+    torch.cuda.empty_cache()
     kw = dict(n=512, q_f=27, q_g=19, forcing="shift", storage=storage, u0=0.05, re=3200.0,
               fr=0.5, sc=0.7, g_over_n=0.02, noise_amp=1e-6, seed=0)
     aa = gpu_sim(layout="aa", **kw)
