@@ -73,17 +73,20 @@ def test_free_streaming_row_aligned_odd_step(storage):
 
 @pytest.mark.parametrize("n,storage,q_f,q_g", [(320, "fp32", 27, 19), (256, "fp32", 27, 19), (512, "fp32", 27, 19),
                                                (512, "fp16", 27, 19), (512, "bf16", 27, 19),
-                                               (256, "fp32", 19, 19), (256, "fp32", 7, 27), (256, "fp16", 27, 7)])
+                                               (256, "fp32", 19, 19), (256, "fp32", 7, 27), (256, "fp16", 27, 7),
+                                               (768, "fp16", 27, 19)])
 def test_free_streaming_sampled_large(n, storage, q_f, q_g):
     # 320^3: rows split over 5 blocks, XCD-ordered shifted odd step; 256^3: the row-aligned
     # odd step on whole rows; 512^3: the row-aligned odd step whose seam lanes reach across
-    # block edges.  Two calls cover an even and an odd step.
+    # block edges; 768^3: three blocks per row, the middle one with a seam at both edges.
+    # Two calls cover an even and an odd step.
+    torch.cuda.empty_cache()
     print(f"\nfree streaming sampled n={n} {storage} {q_f}x{q_g}", flush=True)
     sim = make_sim(n, q_f, q_g, storage)
     sim.load(index_pattern_state(q_f + q_g, n, "cuda:0"), step=0)
     e = np.concatenate([lat.BY_Q[q_f].e, lat.BY_Q[q_g].e])          # (q, 3) as (x, y, z)
     pts = sample_nodes(n, 3000, seed=n)
-    edges = sorted({v for v in (0, 1, 63, 64, 255, 256, n - 2, n - 1) if 0 <= v < n})
+    edges = sorted({v for v in (0, 1, 63, 64, 255, 256, 511, 512, n - 2, n - 1) if 0 <= v < n})
     pts += [(z, y, x) for z in (0, n // 2, n - 1) for y in (0, n - 1) for x in edges]
     zyx = np.array(pts, dtype=np.int64)
     idx = torch.from_numpy(zyx).to("cuda:0")
