@@ -140,7 +140,7 @@ int lbm_step(lbm_ctx* ctx, int64_t n);
 
 /* Queue n >= 0 free-streaming steps: the streaming half of Eqs. (5) and (11)
  * alone (no collision, no force), with the step's own loads, stores, launch
- * shape and block order.  Every population moves one link along its velocity
+ * shape, block order and resident-block caps.  Every population moves one link along its velocity
  * per step, exactly (values are moved, never rounded), and the step counter
  * and layout parity advance as in lbm_step.  Afterwards the state is no longer
  * the method's; the call measures the memory-access ceiling of the step and
