@@ -140,11 +140,12 @@ int lbm_step(lbm_ctx* ctx, int64_t n);
 
 /* Queue n >= 0 free-streaming steps: the streaming half of Eqs. (5) and (11)
  * alone (no collision, no force), with the step's own loads, stores, launch
- * shape, block order and resident-block caps.  Every population moves one link along its velocity
- * per step, exactly (values are moved, never rounded), and the step counter
- * and layout parity advance as in lbm_step.  Afterwards the state is no longer
- * the method's; the call measures the memory-access ceiling of the step and
- * checks the streaming layout.  Queues no diagnostics. */
+ * shape, block order and resident-block caps.  Every population moves one
+ * link along its velocity per step, exactly (values are moved, never
+ * rounded), and the step counter and layout parity advance as in lbm_step.
+ * Afterwards the state is no longer the method's; the call measures the
+ * memory-access ceiling of the step and checks the streaming layout.  Queues
+ * no diagnostics. */
 int lbm_stream(lbm_ctx* ctx, int64_t n);
 
 /* Queue a diagnostic record of the current state (without stepping). */
