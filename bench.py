@@ -22,8 +22,9 @@ BF16 weight-shifted storage, of FP64 arithmetic, of every stencil pair (FP32, an
 FP16 for the D3Q7-scalar sweep) and of the learned 64^3 step, and their energy /
 dissipation histories (E_k, E_p, eps_k, eps_p, -dE/dt) to t = 30 against the plain
 FP32 256^3 run of the same stratified TGV (Fr 0.6); the 512^3 FP16 case with its
-counter traffic; the 128^3 Fr 0.5 case beside the oracle's 64^3 histories; and the
-256^3 Froude sweep (Fr 0.3, 1, 3: FP16 against FP32 storage, Guo against the shift).
+counter traffic, and its 2000-step run against the FP32 run of the same flow; the
+128^3 Fr 0.5 case beside the oracle's 64^3 histories; and the 256^3 Froude sweep (Fr 0.3, 1, 3: FP16 against FP32 storage; at Fr 0.3 Guo against the
+shift, and Guo in FP16 against Guo in FP32).
 """
 import argparse
 import json
@@ -194,7 +195,8 @@ def sweep_128(stgv, stream, steps, warmup):
 def sweep_256_fr(stgv, steps=10000, every=16):
     """The 256^3 Froude sweep (D3Q27x19, velocity shift, Re 1600, Sc 0.7, G/N 0.02, 10000 steps,
     t = 12.3): relative L2 errors of the FP16-storage histories against the FP32 run at each
-    Fr, and at Fr 0.3 the Guo source-term run against the velocity shift."""
+    Fr, and at Fr 0.3 the Guo source-term run against the velocity shift and Guo with FP16
+    storage against Guo with FP32."""
     import torch
     from paper_2605_14505_amd import learned
     out = {"workload": f"256^3 D3Q27x19, Re 1600, Sc 0.7, G/N 0.02, {steps} steps, records every {every}; "
@@ -215,11 +217,46 @@ def sweep_256_fr(stgv, steps=10000, every=16):
         e16 = learned.series_errors(run(storage="fp16", **phys), ref)
         row = {"fp16_vs_fp32": {k: (round(v, 6) if isinstance(v, float) else v) for k, v in e16.items() if k in keep}}
         if fr == 0.3:
-            eg = learned.series_errors(run(**dict(phys, forcing="guo")), ref)
+            guo = run(**dict(phys, forcing="guo"))
+            eg = learned.series_errors(guo, ref)
             row["guo_vs_shift_fp32"] = {k: (round(v, 6) if isinstance(v, float) else v)
                                         for k, v in eg.items() if k in keep}
+            eg16 = learned.series_errors(run(storage="fp16", **dict(phys, forcing="guo")), guo)
+            row["guo_fp16_vs_guo_fp32"] = {k: (round(v, 6) if isinstance(v, float) else v)
+                                           for k, v in eg16.items() if k in keep}
         out[f"fr_{fr:g}"] = row
     return out
+
+
+def run_512(stgv, steps=2000, every=100):
+    """The 512^3 case (D3Q27x19, velocity shift, Re 3200, Fr 0.5, Sc 0.7, G/N 0.02, 2000 steps,
+    t = 1.23): FP16 storage in the AA layout (12.35 GB) and the FP32 run of the same flow
+    (24.7 GB): whole-run MLUPS with diagnostics every `every` steps, whether both stay
+    finite, and the relative L2 errors of the FP16 histories against the FP32 ones."""
+    import time
+    import torch
+    from paper_2605_14505_amd import learned
+    phys = learned.physics(0.5, re=3200.0)
+    recs, rate = {}, {}
+    for storage in ("fp16", "fp32"):
+        sim = stgv.Simulation(diag_every=every, n=512, q_f=27, q_g=19, storage=storage, **phys)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps + 1)
+        torch.cuda.synchronize()
+        rate[storage] = round(512 ** 3 * (steps + 1) / (time.perf_counter() - t0) / 1e6, 1)
+        recs[storage] = sim.diagnostics(raise_unstable=False)
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    keep = ("finite", "ek", "ep", "eps_k", "eps_p", "dEdt")
+    e16 = learned.series_errors(recs["fp16"], recs["fp32"])
+    return {"workload": f"512^3 D3Q27x19 velocity shift, Re 3200, Fr 0.5, Sc 0.7, G/N 0.02, {steps} steps "
+                        f"(t = 1.23), records every {every}",
+            "run_mlups_fp16": rate["fp16"], "run_mlups_fp32": rate["fp32"],
+            "finite_fp16": all(r["nonfinite"] == 0 for r in recs["fp16"]),
+            "finite_fp32": all(r["nonfinite"] == 0 for r in recs["fp32"]),
+            "fp16_vs_fp32": {k: (round(v, 6) if isinstance(v, float) else v) for k, v in e16.items() if k in keep}}
 
 
 def forms(stgv, stream, t_end, steps, warmup):
@@ -263,6 +300,8 @@ def forms(stgv, stream, t_end, steps, warmup):
                              "hbm_frac": round(184 * 512 ** 3 / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
                              "traffic": traffic, "traffic_source": traffic_src}
     progress("forms: 512^3 FP16 timing done")
+    out["run_512"] = run_512(stgv)
+    progress("forms: 512^3 2000-step FP16 and FP32 runs done")
     out["sweep_128_fr05"] = sweep_128(stgv, stream, steps, warmup)
     progress("forms: 128^3 Fr 0.5 run done")
     out["sweep_256_fr"] = sweep_256_fr(stgv)
