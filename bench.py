@@ -195,17 +195,19 @@ def sweep_128(stgv, stream, steps, warmup):
 def sweep_256_fr(stgv, steps=10000, every=16):
     """The 256^3 Froude sweep (D3Q27x19, velocity shift, Re 1600, Sc 0.7, G/N 0.02, 10000 steps,
     t = 12.3): relative L2 errors of the FP16-storage histories against the FP32 run at each
-    Fr, and at Fr 0.3 the Guo source-term run against the velocity shift and Guo with FP16
-    storage against Guo with FP32."""
+    Fr (and, over 5000 steps, for the D3Q27xD3Q7 and D3Q19xD3Q7 pairs), and at Fr 0.3 the
+    Guo source-term run against the velocity shift and Guo with FP16 storage against Guo
+    with FP32."""
     import torch
     from paper_2605_14505_amd import learned
     out = {"workload": f"256^3 D3Q27x19, Re 1600, Sc 0.7, G/N 0.02, {steps} steps, records every {every}; "
                        "relative L2 errors of the histories"}
     keep = ("finite", "ek", "ep", "eps_k", "eps_p", "dEdt")
 
-    def run(**kw):
-        sim = stgv.Simulation(diag_every=every, n=256, q_f=27, q_g=19, **kw)
-        sim.step(steps + 1)
+    def run(n_steps=steps, **kw):
+        kw = dict(dict(q_f=27, q_g=19), **kw)
+        sim = stgv.Simulation(diag_every=every, n=256, **kw)
+        sim.step(n_steps + 1)
         torch.cuda.synchronize()
         recs = sim.diagnostics(raise_unstable=False)
         sim.close()
@@ -224,6 +226,12 @@ def sweep_256_fr(stgv, steps=10000, every=16):
             eg16 = learned.series_errors(run(storage="fp16", **dict(phys, forcing="guo")), guo)
             row["guo_fp16_vs_guo_fp32"] = {k: (round(v, 6) if isinstance(v, float) else v)
                                            for k, v in eg16.items() if k in keep}
+        # the D3Q7-scalar pairs of the sweep, FP16 against FP32 storage, over 5000 steps
+        for qf, qg in ((27, 7), (19, 7)):
+            ref_p = run(n_steps=steps // 2, q_f=qf, q_g=qg, **phys)
+            ep = learned.series_errors(run(n_steps=steps // 2, q_f=qf, q_g=qg, storage="fp16", **phys), ref_p)
+            row[f"fp16_vs_fp32_{qf}x{qg}_{steps // 2}_steps"] = {
+                k: (round(v, 6) if isinstance(v, float) else v) for k, v in ep.items() if k in keep}
         out[f"fr_{fr:g}"] = row
     return out
 
