@@ -288,6 +288,20 @@ def test_aa_equals_ab_bitwise_whole_row_blocks(storage, n, q_f, q_g):
 
 
 @pytest.mark.parametrize("forcing", ["guo", "edm", "hcz"])
+def test_aa_equals_ab_bitwise_whole_row_blocks_other_forcings(forcing):
+    # the row-aligned odd step (FP32, 256^3) with the other forcing schemes
+    kw = c1_kw(n=256, forcing=forcing, g_over_n=0.02)
+    aa = gpu_sim(layout="aa", **kw)
+    ab = gpu_sim(layout="ab", **kw)
+    for k in (1, 2):                  # ends at odd, odd step counts
+        aa.step(k)
+        ab.step(k)
+        assert torch.equal(aa.populations(), ab.populations()), k
+    aa.close()
+    ab.close()
+
+
+@pytest.mark.parametrize("forcing", ["guo", "edm", "hcz"])
 def test_aa_equals_ab_bitwise_other_forcings(forcing):
     kw = c1_kw(n=16, forcing=forcing)
     aa = gpu_sim(layout="aa", **kw)
