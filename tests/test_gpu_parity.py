@@ -488,6 +488,26 @@ def test_full_size_256_sampled_parity(forcing):
         _sampled_patch_parity(kw, steps, 24, tol=4e-6 * steps)
 
 
+@pytest.mark.parametrize("storage,u", [("fp16", 2.0 ** -11), ("bf16", 2.0 ** -8)])
+def test_full_size_256_reduced_storage_sampled_parity(storage, u):
+    # 256^3 with 2-byte storage: the odd step (step 2) runs row-aligned through the LDS ring
+    # on whole rows.  Against the FP64 oracle the error is the storage rounding: one
+    # rounding of the initial deviations and one per step, each at most u of a deviation.
+    kw = dict(n=256, q_f=27, q_g=19, forcing="shift", storage=storage, u0=0.05, re=1600.0, fr=1.0,
+              sc=0.7, g_over_n=0.02, noise_amp=1e-6, seed=0)
+    for steps in (1, 2):
+        _sampled_patch_parity(kw, steps, 16, tol=(steps + 2) * u)
+
+
+@pytest.mark.parametrize("q_f,q_g", [(19, 19), (7, 27)])
+def test_full_size_256_ring_pairs_sampled_parity(q_f, q_g):
+    # the other stencil pairs whose FP32 odd step runs row-aligned at 256^3
+    kw = dict(n=256, q_f=q_f, q_g=q_g, forcing="shift", u0=0.05, re=1600.0, fr=1.0, sc=0.7,
+              g_over_n=0.02, noise_amp=1e-6, seed=0)
+    for steps in (1, 2):
+        _sampled_patch_parity(kw, steps, 16, tol=4e-6 * steps)
+
+
 def test_large_512_fp16_sampled_parity():
     # the 512^3 single-GPU case: FP16 weight-shifted storage in the AA layout (12.35 GB),
     # velocity shift, Re 3200, Fr 0.5.  Against the FP64 oracle the error is FP16 storage
