@@ -64,6 +64,17 @@ def read_traffic(workload_key, n3, bytes_per_node):
         return None, "malformed counter summary"
 
 
+def host_cpu_model():
+    """The host CPU's model name (Linux), or None."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(n, steps, forcing):
     """The FP64 oracle as it stands, single-threaded BLAS, on a bounded sample of the workload."""
     from threadpoolctl import threadpool_limits
@@ -502,6 +513,7 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_n, args.cpu_sample_steps, args.forcing)
         out["cpu_baseline"]["host_threads_available"] = os.cpu_count()
+        out["cpu_baseline"]["host_cpu"] = host_cpu_model()
         progress("CPU oracle baseline done")
     if not args.no_energy_error:
         out["energy_error"] = energy_error(stgv)
