@@ -14,8 +14,8 @@
 //              populations the lane owns.
 // The MFMA A operands (the two moment tables and the three weight matrices, 34 KB of
 // BF16) are staged in LDS once per block behind one barrier; the diagnostic reduction
-// adds its own.  Launched with 256-thread blocks over n^3 / 128 blocks (n % 64 == 0,
-// n <= 256).
+// adds its own.  Launched with 256-thread blocks on an (n / 64, n / 2, n) grid, each block
+// two 32-node runs in each of two x-rows (n % 64 == 0, n <= 256).
 #include "lbm_kernels.hpp"
 #include "learned.hpp"
 #include "mlp_device.hpp"
@@ -37,16 +37,33 @@ __device__ __forceinline__ float xor32(float v) { return __shfl_xor(v, 32, 64); 
 #endif
 constexpr int PW_IN = K_IN + STGV_LEARNED_W_PAD, PW_HID = N_HID + STGV_LEARNED_W_PAD;
 
-// rows x cols bf16 (cols a multiple of 8) from global, row-major, into LDS rows of pitch
-// `pitch`, in 16-byte pieces spread over the block
-__device__ __forceinline__ void stage_rows(uint16_t* d, const uint16_t* __restrict__ g, int rows,
-                                           int cols, int pitch) {
-  const int per_row = cols / 8;
-  for (int i = (int)threadIdx.x; i < rows * per_row; i += (int)blockDim.x) {
-    const int r = i / per_row, c = i - r * per_row;
-    *reinterpret_cast<uint4*>(d + r * pitch + 8 * c) = reinterpret_cast<const uint4*>(g)[i];
+// A ROWS x COLS BF16 table (COLS a multiple of 8), row-major in global memory, on its way
+// to LDS rows of pitch PITCH: this thread's 16-byte pieces of the 256-thread block's share
+// are loaded into registers first (load) and written to LDS later (put), so that a block
+// issues the loads of every table before it waits for any of them.
+constexpr int kStageThreads = 256;
+using u32x4 = unsigned int __attribute__((ext_vector_type(4)));
+template <int ROWS, int COLS, int PITCH>
+struct Staged {
+  static constexpr int per_row = COLS / 8, pieces = ROWS * per_row;
+  static_assert(pieces > kStageThreads && pieces <= 2 * kStageThreads, "two pieces per thread");
+  u32x4 t0, t1;   // named registers: an array member here was placed in scratch memory
+  __device__ __forceinline__ void load(const uint16_t* __restrict__ g) {
+    const int i = (int)threadIdx.x;
+    t0 = reinterpret_cast<const u32x4*>(g)[i];
+    // unconditional (past the end: the last piece again), so no load waits on a branch
+    t1 = reinterpret_cast<const u32x4*>(g)[min(i + kStageThreads, pieces - 1)];
   }
-}
+  __device__ __forceinline__ void put(uint16_t* d) const {
+    auto at = [d](int i) {
+      const int r = i / per_row, c = i - r * per_row;
+      return reinterpret_cast<u32x4*>(d + r * PITCH + 8 * c);
+    };
+    const int i = (int)threadIdx.x;
+    *at(i) = t0;
+    if (i + kStageThreads < pieces) *at(i + kStageThreads) = t1;
+  }
+};
 
 __device__ __forceinline__ f32x16 mfma16(const bf16x8& a, const bf16x8& b, const f32x16& c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
@@ -142,24 +159,29 @@ __global__ __launch_bounds__(256) void learned_step_kernel(float* __restrict__ p
   const int n = geo.n;
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5, col = lane & 31;
-  const uint32_t un = (uint32_t)n;
-  const uint32_t node = blockIdx.x * 128u + (threadIdx.x >> 6) * 32u + (uint32_t)col;
-  const NodeIndex ix = make_index((int)(node % un), (int)((node / un) % un), (int)(node / (un * un)), n);
+  // A wavefront holds 32 consecutive nodes of one x-row (rows are a whole number of
+  // 64-node segments), a block two such runs in each of two rows; the row and plane are
+  // the wavefront's own, so only x is per lane and nothing is divided.
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int y = 2 * (int)blockIdx.y + (wv >> 1), z = (int)blockIdx.z;
+  const int x0 = 64 * (int)blockIdx.x + 32 * (wv & 1);
+  const NodeIndex ix = make_index(x0 + col, y, z, n);
   const float* src = pop;
 
-  // The MFMA A operands (feature and correction tables, the three permuted weight
-  // matrices, 34 KB unpadded) are shared by every node: staged in LDS once per block, they
-  // are read there instead of through the vector cache (64^3 step 40.2 -> 33.9 us).
-  __shared__ alignas(16) uint16_t s_feat[64 * PW_IN], s_minv[64 * PW_IN], s_w1p[64 * PW_IN];
-  __shared__ alignas(16) uint16_t s_w2p[64 * PW_HID], s_w3p[64 * PW_HID];
-  stage_rows(s_feat, P->tab.feat, 64, K_IN, PW_IN);
-  stage_rows(s_minv, P->tab.minv, 64, K_IN, PW_IN);
-  stage_rows(s_w1p, P->w1p, 64, K_IN, PW_IN);
-  stage_rows(s_w2p, P->w2p, 64, N_HID, PW_HID);
-  stage_rows(s_w3p, P->w3p, 64, N_HID, PW_HID);
-  __syncthreads();
-
-  // ---- this half's populations
+  // ---- this half's populations.  The halves of a slot read neighbouring arrays
+  // (a1 = a0 +- 1): the address is the lower array's base, uniform, plus the node offset
+  // and, for the half owning the upper array, one array stride.
+  const uint32_t S = (uint32_t)geo.stride;
+  const uint32_t upper_h1 = h ? S : 0u, upper_h0 = h ? 0u : S;
+  auto slot_address = [&](auto* base, int p0, int p1, int a0, int a1, uint32_t off) {
+    int lower;
+    uint32_t extra;
+    if (p1 < 0) { lower = a0; extra = 0u; }                       // half 0 only
+    else if (a1 == a0 + 1) { lower = a0; extra = upper_h1; }
+    else if (a0 == a1 + 1) { lower = a1; extra = upper_h0; }
+    else { lower = 0; extra = (uint32_t)(h ? a1 : a0) * S; }
+    return at_byte(base + (size_t)lower * S, (off + extra) * 4u);
+  };
   float v[NSLOT];
 #pragma unroll
   for (int s = 0; s < NSLOT; ++s) {
@@ -169,12 +191,35 @@ __global__ __launch_bounds__(256) void learned_step_kernel(float* __restrict__ p
     if (p0 >= 0) address_of<MODE, true>(p0, ix, a0, o0);
     if (p1 >= 0) address_of<MODE, true>(p1, ix, a1, o1);
     v[s] = 0.f;
-    if ((h ? p1 : p0) >= 0) {
-      const int arr = h ? a1 : a0;
-      const uint32_t off = h ? o1 : o0;
-      v[s] = load_as<float>(at_byte(src, ((uint32_t)arr * (uint32_t)geo.stride + off) * 4u));
-    }
+    if ((h ? p1 : p0) >= 0) v[s] = load_as<float>(slot_address(src, p0, p1, a0, a1, h ? o1 : o0));
   }
+
+  // The MFMA A operands (feature and correction tables, the three permuted weight
+  // matrices, 34 KB unpadded) are shared by every node: staged in LDS once per block, they
+  // are read there instead of through the vector cache (64^3 step 40.2 -> 33.9 us).  Their
+  // loads are issued behind the population loads and before any wait, so the block pays
+  // one memory latency for both.
+  __shared__ alignas(16) uint16_t s_feat[64 * PW_IN], s_minv[64 * PW_IN], s_w1p[64 * PW_IN];
+  __shared__ alignas(16) uint16_t s_w2p[64 * PW_HID], s_w3p[64 * PW_HID];
+  {
+    Staged<64, K_IN, PW_IN> feat, minv, w1;
+    Staged<64, N_HID, PW_HID> w2, w3;
+    feat.load(P->tab.feat);
+    minv.load(P->tab.minv);
+    w1.load(P->w1p);
+    w2.load(P->w2p);
+    w3.load(P->w3p);
+    // every staged value is an input here, so the wave waits once, for all of the loads,
+    // and no LDS write is scheduled above a load still to be issued
+    asm volatile("" ::"v"(feat.t0), "v"(feat.t1), "v"(minv.t0), "v"(minv.t1), "v"(w1.t0), "v"(w1.t1),
+                 "v"(w2.t0), "v"(w2.t1), "v"(w3.t0), "v"(w3.t1));
+    feat.put(s_feat);
+    minv.put(s_minv);
+    w1.put(s_w1p);
+    w2.put(s_w2p);
+    w3.put(s_w3p);
+  }
+  __syncthreads();
   // Direction of slot s in this half: sg * e0(s), e0 the half-0 direction; the
   // weight is the same in both halves except for half 1's two empty slots.
   const float sg = h ? -1.f : 1.f;
@@ -369,11 +414,12 @@ __global__ __launch_bounds__(256) void learned_step_kernel(float* __restrict__ p
       if (16 * mt + r < NSLOT) v[16 * mt + r] += acc[r];
   }
 
-  // ---- store (the node's neighbour offsets are recomputed here rather than kept
-  // live through the network: the empty asm hides that the index is unchanged)
-  uint32_t node_s = node;
-  asm volatile("" : "+v"(node_s));
-  const NodeIndex ixs = make_index((int)(node_s % un), (int)((node_s / un) % un), (int)(node_s / (un * un)), n);
+  // ---- store, addressed as the loads (the node's neighbour offsets are recomputed here
+  // rather than kept live through the network: the empty asm hides that the lane's x is
+  // unchanged)
+  int col_s = col;
+  asm volatile("" : "+v"(col_s));
+  const NodeIndex ixs = make_index(x0 + col_s, y, z, n);
 #pragma unroll
   for (int s = 0; s < NSLOT; ++s) {
     const int p0 = owned_pop(0, s), p1 = owned_pop(1, s);
@@ -381,11 +427,7 @@ __global__ __launch_bounds__(256) void learned_step_kernel(float* __restrict__ p
     uint32_t o0 = 0, o1 = 0;
     if (p0 >= 0) address_of<MODE, false>(p0, ixs, a0, o0);
     if (p1 >= 0) address_of<MODE, false>(p1, ixs, a1, o1);
-    if ((h ? p1 : p0) >= 0) {
-      const int arr = h ? a1 : a0;
-      const uint32_t off = h ? o1 : o0;
-      store_as(at_byte(dst, ((uint32_t)arr * (uint32_t)geo.stride + off) * 4u), v[s]);
-    }
+    if ((h ? p1 : p0) >= 0) store_as(slot_address(dst, p0, p1, a0, a1, h ? o1 : o0), v[s]);
   }
 
   if constexpr (DIAG) {
@@ -396,14 +438,15 @@ __global__ __launch_bounds__(256) void learned_step_kernel(float* __restrict__ p
       write_fields(m, fields, ixs.base, (int64_t)n * n * n);
       node_partials(m, c, acc);
     }
-    block_reduce_store<NPART, (1u << P_UMAX2)>(acc, partials + (int64_t)blockIdx.x * NPART);
+    const int64_t blk = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
+    block_reduce_store<NPART, (1u << P_UMAX2)>(acc, partials + blk * NPART);
   }
 }
 
 template <int FORCE, int MODE>
 hipError_t go(bool diag, int n, hipStream_t st, float* pop, float* dst, Geometry geo, PhysConsts c,
               float* fields, double* partials, const void* net) {
-  const dim3 block(256), grid((unsigned)((int64_t)n * n * n / 128));
+  const dim3 block(256), grid((unsigned)(n / 64), (unsigned)(n / 2), (unsigned)n);   // n^3 / 128 blocks
   const Packed* P = static_cast<const Packed*>(net);
   if (diag)
     hipLaunchKernelGGL((learned_step_kernel<FORCE, MODE, true>), grid, block, 0, st, pop, dst, geo, c, fields,

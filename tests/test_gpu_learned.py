@@ -13,7 +13,7 @@ FP32 rounding level.
 import numpy as np
 import pytest
 
-from inputs import uniform_deviations
+from inputs import sample_nodes, uniform_deviations
 from oracle import lattice as lat, learned as L, model
 
 torch = pytest.importorskip("torch")
@@ -352,6 +352,61 @@ def test_learned_step_matches_oracle(layout, before):
     e = lf.e.astype(float)
     dcorr_f = got[:27] - plain[:27]
     assert abs(dcorr_f.sum()) < 1e-9 * dcorr_f.size
+
+
+@pytest.mark.parametrize("n,layout,before,forcing", [(128, "aa", 2, "shift"), (128, "aa", 3, "shift"),
+                                                     (192, "aa", 3, "guo"), (192, "ab", 2, "shift")])
+def test_learned_step_sampled_parity_wider_boxes(n, layout, before, forcing):
+    # n = 128 and 192 put two and three blocks along each row (64^3 has one).  A node's
+    # value after the step is the collision at x - e_i, so the oracle runs on the 3 x 3 x 3
+    # patch of pre-step populations around each sampled node, the samples including the
+    # edges of the blocks' 32-node runs and of their row pairs.
+    torch.cuda.empty_cache()
+    kw = _learned_kw(n=n, forcing=forcing, re=800.0)
+    rng = np.random.default_rng(5)
+    theta = L.init_params(5) + 0.01 * rng.standard_normal(L.N_PARAMS)
+    sim = stgv.Simulation(layout=layout, **kw)
+    sim.step(before)                                      # even (2) or odd (3) AA parity next
+    xs_edge = sorted({0, 31, 32, 63, 64, 127, 128, n - 65, n - 64, n - 1} & set(range(n)))
+    pts = sorted(set(sample_nodes(n, 40, seed=n + before))
+                 | {(z, y, x) for z in (0, n - 1) for y in (0, 1, 2, n - 1) for x in xs_edge})
+    c = np.array(pts, dtype=np.int64)                                      # (m, 3) as (z, y, x)
+    d = np.array([(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)])
+    patch = torch.from_numpy(((c[:, None, :] + d[None]) % n).reshape(-1, 3)).to(DEV)
+    pops = sim.populations()
+    pre = pops[:, patch[:, 0], patch[:, 1], patch[:, 2]].cpu().numpy().astype(np.float64)
+    del pops
+    m = len(pts)
+    pre = pre.reshape(46, m, 3, 3, 3)
+    lf, lg = lat.D3Q27, lat.D3Q19
+    wf, wg = lf.w[:, None, None, None], lg.w[:, None, None, None]
+    U = model.units(model.Params(**kw))
+    xs = np.concatenate([L.features(pre[:27, k] + wf, pre[27:, k] + wg, U).reshape(47, -1).T
+                         for k in range(m)])
+    mean, iscale, _ = L.norm_from_data(xs, np.ones((1, 41)))
+    norm = (mean, iscale, np.full(41, 1e-6))
+    sim.set_mlp(packed_net(theta, norm))
+    sim.step(1)
+    idx = torch.from_numpy(c).to(DEV)
+    pops = sim.populations()
+    got = pops[:, idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy().astype(np.float64)   # (46, m)
+    del pops
+    ref, plain = np.empty_like(got), np.empty_like(got)
+    for k in range(m):
+        f0, g0 = pre[:27, k] + wf, pre[27:, k] + wg
+        fs, gs, _ = L.learned_collide(f0, g0, U, theta, norm)
+        fp, gp, _ = model.collide(f0, g0, lf, lg, U)
+        ref[:, k] = np.concatenate([model.stream(fs, lf)[:, 1, 1, 1] - lf.w,
+                                    model.stream(gs, lg)[:, 1, 1, 1] - lg.w])
+        plain[:, k] = np.concatenate([model.stream(fp, lf)[:, 1, 1, 1] - lf.w,
+                                      model.stream(gp, lg)[:, 1, 1, 1] - lg.w])
+    corr = ref - plain
+    err_corr = np.abs((got - plain) - corr).max() / np.abs(corr).max()
+    print(f"\nlearned step n={n} ({layout}, after {before}, {forcing}), {m} nodes: correction "
+          f"magnitude {np.abs(corr).max():.3e}, relative error {err_corr:.3e}")
+    assert err_corr < 0.05
+    sim.close()
+    torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("forcing", ["edm", "hcz"])
