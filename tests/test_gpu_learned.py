@@ -355,9 +355,11 @@ def test_learned_step_matches_oracle(layout, before):
 
 
 @pytest.mark.parametrize("n,layout,before,forcing", [(128, "aa", 2, "shift"), (128, "aa", 3, "shift"),
-                                                     (192, "aa", 3, "guo"), (192, "ab", 2, "shift")])
+                                                     (192, "aa", 3, "guo"), (192, "ab", 2, "shift"),
+                                                     (256, "aa", 3, "shift")])
 def test_learned_step_sampled_parity_wider_boxes(n, layout, before, forcing):
-    # n = 128 and 192 put two and three blocks along each row (64^3 has one).  A node's
+    # n = 128 and 192 put two and three blocks along each row (64^3 has one); 256 is the
+    # largest box the learned form takes (3.1 GB of state behind one base).  A node's
     # value after the step is the collision at x - e_i, so the oracle runs on the 3 x 3 x 3
     # patch of pre-step populations around each sampled node, the samples including the
     # edges of the blocks' 32-node runs and of their row pairs.
@@ -404,7 +406,9 @@ def test_learned_step_sampled_parity_wider_boxes(n, layout, before, forcing):
     err_corr = np.abs((got - plain) - corr).max() / np.abs(corr).max()
     print(f"\nlearned step n={n} ({layout}, after {before}, {forcing}), {m} nodes: correction "
           f"magnitude {np.abs(corr).max():.3e}, relative error {err_corr:.3e}")
-    assert err_corr < 0.05
+    # BF16 operands (2^-9 relative each) put the correction ~4e-3 off; a wrong slot,
+    # node or array is off by O(1)
+    assert err_corr < 0.02
     sim.close()
     torch.cuda.empty_cache()
 
