@@ -98,10 +98,9 @@ __device__ __forceinline__ Dir dir_of(int p) {
   return d;
 }
 
-// A lattice of up to 256^3 nodes (46 arrays, FP32) spans less than 4 GiB, so a
-// population is addressed as the lattice's base, uniform across the wavefront, plus
-// a 32-bit byte offset that folds in the lane's own array (the halves of a node own
-// different arrays).
+// A population is addressed as a base uniform across the wavefront (the lower of the
+// two neighbouring arrays a slot's halves own) plus a 32-bit byte offset: the node's
+// offset and, for the half owning the upper array, one array stride.
 __device__ __forceinline__ const float* at_byte(const float* base, uint32_t bytes) {
   return (const float*)((const char*)base + bytes);
 }
@@ -472,7 +471,7 @@ hipError_t by_mode(int mode, bool diag, int n, hipStream_t st, float* pop, float
 hipError_t launch_learned_step(int forcing, int mode, int flags, int n, hipStream_t st, float* pop,
                                float* dst, Geometry geo, PhysConsts c, float* fields, double* partials,
                                const void* packed) {
-  if (n % 64 != 0 || n > 256) return hipErrorInvalidValue;     // 32-bit byte offsets
+  if (n % 64 != 0 || n > 256) return hipErrorInvalidValue;     // the boxes lbm_set_mlp accepts
   const bool diag = (flags & K_PARTIALS) != 0;
   if (forcing == FORCE_GUO) return by_mode<FORCE_GUO>(mode, diag, n, st, pop, dst, geo, c, fields, partials, packed);
   if (forcing == FORCE_SHIFT) return by_mode<FORCE_SHIFT>(mode, diag, n, st, pop, dst, geo, c, fields, partials, packed);

@@ -28,12 +28,21 @@ STEP_SOURCES = ("stencil.hpp", "lbm_device.hpp", "mlp_device.hpp", "lbm_kernels.
                 "lbm_instances.hpp", "lbm_fp32.hip", "lbm_fp16.hip", "lbm_bf16.hip", "learned_step.hip")
 
 
+def code_only(src):
+    """C++ source without its comments and with every whitespace run made one space, so that
+    a hash of it follows the code the kernels are compiled from, not the comments.  (None of
+    the hashed sources has a comment marker inside a string literal.)"""
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return " ".join(src.split())
+
+
 def kernel_source_hash():
     csrc = os.path.join(ROOT, "paper_2605_14505_amd", "csrc")
     h = hashlib.sha256()
     for f in STEP_SOURCES:
         h.update(f.encode())
-        h.update(open(os.path.join(csrc, f), "rb").read())
+        h.update(code_only(open(os.path.join(csrc, f), encoding="utf-8").read()).encode())
     return h.hexdigest()[:16]
 
 

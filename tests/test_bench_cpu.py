@@ -51,3 +51,13 @@ def test_cpu_baseline_record():
     assert rec["unit"] == "MLUPS" and rec["kind"] == "oracle" and rec["cores"] == 1
     assert rec["value"] > 0
     assert "8^3" in rec["sample"]
+
+
+def test_source_hash_follows_code_not_comments():
+    # the counters' source hash ignores comments and layout, and sees any change of code
+    from paper_2605_14505_amd.profsummary import code_only
+    a = "int f(int x) {  // doubles\n  return 2 * x; /* one line */\n}\n"
+    b = "int f(int x) {\n  /* a longer\n     comment */ return 2 * x;\n}  // done\n"
+    c = "int f(int x) {\n  return 3 * x;\n}\n"
+    assert code_only(a) == code_only(b) == "int f(int x) { return 2 * x; }"
+    assert code_only(c) != code_only(a)
