@@ -316,6 +316,35 @@ def test_zero_output_layer_reproduces_the_plain_step(forcing):
         f, g = (a + w)[:27], (a + w)[27:]
 
 
+@pytest.mark.parametrize("n,layout", [(64, "aa"), (128, "aa"), (128, "ab")])
+def test_learned_diagnostics_match_the_plain_step(n, layout):
+    # The learned step's diagnostic instance writes the fields and the FP64 partials of its
+    # own blocks.  With a zero output layer it is the plain step to FP32 rounding, so every
+    # record must be the plain run's to ~1e-7; a block whose partials were missed or
+    # counted twice moves the energies by percents.
+    kw = _learned_kw(n=n, forcing="shift", noise_amp=1e-3)
+    theta = L.unpack(L.init_params(3))
+    theta["W3"][:] = 0.0
+    theta["b3"][:] = 0.0
+    packed = packed_net(L.pack(theta), (np.zeros(47), np.ones(47), np.ones(41)))
+    plain = stgv.Simulation(layout=layout, diag_every=2, **kw)
+    learned = stgv.Simulation(layout=layout, diag_every=2, **kw)
+    learned.set_mlp(packed)
+    plain.step(7)
+    learned.step(7)
+    rp, rl = plain.diagnostics(), learned.diagnostics()
+    assert len(rp) == len(rl) >= 4
+    worst = 0.0
+    for a, b in zip(rp, rl):
+        assert a["step"] == b["step"] and b["nonfinite"] == 0
+        for k in ("ek", "ep", "eps_k", "eps_p", "umax"):
+            worst = max(worst, abs(a[k] - b[k]) / abs(a[k]))
+    print(f"\nlearned vs plain diagnostics, n={n} {layout}: {len(rp)} records, worst rel {worst:.2e}")
+    assert worst < 1e-5                                  # measured: 2e-7
+    plain.close()
+    learned.close()
+
+
 @pytest.mark.parametrize("layout,before", [("aa", 2), ("aa", 3), ("ab", 2)])
 def test_learned_step_matches_oracle(layout, before):
     kw = _learned_kw(n=64, forcing="guo", re=800.0)
