@@ -15,7 +15,7 @@ namespace {
 template <int QF, int QG, int FORCE, typename T, int MODE, int FLAGS>
 hipError_t go_step(const LaunchShape& sh, hipStream_t st, T* pop, T* dst, Geometry geo,
                    PhysConsts c, float* fields, double* partials) {
-  const size_t lds = (MODE == MODE_EVEN && FLAGS == K_COLLIDE) ? even_step_lds(sizeof(T), geo.n, std::is_same<T, bf16_t>::value) : 0;
+  const size_t lds = (MODE == MODE_EVEN && FLAGS == K_COLLIDE) ? even_step_lds(sizeof(T), geo.n) : 0;
   hipLaunchKernelGGL((lbm_step_kernel<QF, QG, FORCE, T, STGV_C, MODE, FLAGS>), sh.grid, sh.block,
                      lds, st, pop, dst, geo, c, fields, partials);
   return hipGetLastError();
@@ -122,7 +122,7 @@ hipError_t launch_stream<STGV_T>(int qf, int qg, int mode, const LaunchShape& sh
         return hipGetLastError(); \
       } \
     } \
-    if (mode == MODE_EVEN) hipLaunchKernelGGL((lbm_stream_kernel<A, B, STGV_T, MODE_EVEN>), sh.grid, sh.block, even_step_lds(sizeof(STGV_T), geo.n, std::is_same<STGV_T, bf16_t>::value), st, pop, dst, geo); \
+    if (mode == MODE_EVEN) hipLaunchKernelGGL((lbm_stream_kernel<A, B, STGV_T, MODE_EVEN>), sh.grid, sh.block, even_step_lds(sizeof(STGV_T), geo.n), st, pop, dst, geo); \
     else if (mode == MODE_ODD) hipLaunchKernelGGL((lbm_stream_kernel<A, B, STGV_T, MODE_ODD>), sh.grid, sh.block, 0, st, pop, dst, geo); \
     else if (mode == MODE_AB) hipLaunchKernelGGL((lbm_stream_kernel<A, B, STGV_T, MODE_AB>), sh.grid, sh.block, 0, st, pop, dst, geo); \
     else return hipErrorInvalidValue; \

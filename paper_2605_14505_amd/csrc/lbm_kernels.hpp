@@ -55,6 +55,16 @@ __device__ __forceinline__ BlockXYZ node_block() {
   return b;
 }
 
+// The BF16 even step is compiled to issue all 46 loads before its first wait, where the
+// FP16 one issues 32, waits, then the rest; at the occupancy caps of even_step_lds that
+// keeps more bytes in flight than the step can use.  An empty asm that takes the 27 f
+// values makes the wavefront wait for them before it issues the g loads.  BF16 even step,
+// ms: 512^3 4.75 -> 4.50 (at FP16's 3 blocks per CU; with a cap of 2 and all loads first
+// 4.59-4.75), 256^3 0.548 -> 0.549.
+template <int MODE, int FLAGS, typename T, int QF>
+constexpr bool kBatchBf16 = MODE == MODE_EVEN && FLAGS == K_COLLIDE && std::is_same<T, bf16_t>::value && QF == 27;
+#define STGV_OPERANDS_27(a) "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5]), "+v"(a[6]), "+v"(a[7]), "+v"(a[8]), "+v"(a[9]), "+v"(a[10]), "+v"(a[11]), "+v"(a[12]), "+v"(a[13]), "+v"(a[14]), "+v"(a[15]), "+v"(a[16]), "+v"(a[17]), "+v"(a[18]), "+v"(a[19]), "+v"(a[20]), "+v"(a[21]), "+v"(a[22]), "+v"(a[23]), "+v"(a[24]), "+v"(a[25]), "+v"(a[26])
+
 template <int QF, int QG, int FORCE, typename T, typename C, int MODE, int FLAGS>
 __global__ STGV_STEP_BOUNDS_FOR(MODE, FLAGS, T, C) void lbm_step_kernel(T* pop, T* dst, Geometry geo,
                                                        PhysConsts c, float* __restrict__ fields,
@@ -76,6 +86,7 @@ __global__ STGV_STEP_BOUNDS_FOR(MODE, FLAGS, T, C) void lbm_step_kernel(T* pop, 
     const NodeIndex ix = make_index(x, y, z, n);
     C f[QF], g[QG];
     gather<QF, T, MODE, true>(f, pop, 0, ix, geo.stride);
+    if constexpr (kBatchBf16<MODE, FLAGS, T, QF>) asm volatile("" : STGV_OPERANDS_27(f) :: "memory");
     gather<QG, T, MODE, true>(g, pop, QF, ix, geo.stride);
     StepMacro<C> m;
     step_macro<QF, QG, FORCE, sizeof(T) == 4>(f, g, c, m);

@@ -80,26 +80,16 @@ inline bool ring_shape(const LaunchShape& sh, int n, size_t elem) {
 // 5.00 -> 4.92, while 256^3 and 128^3 lose with any cap.  The shifted odd step, whose
 // x-shifted lines neighbouring wavefronts share, gains nothing from a cap; the ring odd
 // step has its own (ring_step_lds).
-// BF16 keeps its own cap, 2 blocks per CU from n = 256: its even step is compiled to issue
-// all 46 loads before the first wait (FP16's issues 32 first).  BF16 even step, ms: 512^3
-// 4.88 at 3 blocks per CU -> 4.59 at 2 (FP16 at 2: 4.36 -> 5.55); 256^3 0.552 uncapped ->
-// 0.542.
+// The caps assume a step that issues its loads in two batches; the BF16 even step is made
+// to (lbm_step_kernel), and is then best with FP16's caps.
 #ifndef STGV_EVEN_CAP_FP32
 #define STGV_EVEN_CAP_FP32 2
 #endif
 #ifndef STGV_EVEN_CAP_2B
 #define STGV_EVEN_CAP_2B 3
 #endif
-#ifndef STGV_EVEN_CAP_BF16
-#define STGV_EVEN_CAP_BF16 2
-#endif
-#ifndef STGV_EVEN_CAP_BF16_FROM
-#define STGV_EVEN_CAP_BF16_FROM 256
-#endif
-inline size_t even_step_lds(size_t elem, int n, bool bf16) {
-  const int cap = elem == 4 ? (n >= 256 ? STGV_EVEN_CAP_FP32 : 0)
-                  : bf16    ? (n >= STGV_EVEN_CAP_BF16_FROM ? STGV_EVEN_CAP_BF16 : 0)
-                            : (n >= 512 ? STGV_EVEN_CAP_2B : 0);
+inline size_t even_step_lds(size_t elem, int n) {
+  const int cap = elem == 4 ? (n >= 256 ? STGV_EVEN_CAP_FP32 : 0) : (n >= 512 ? STGV_EVEN_CAP_2B : 0);
   if (cap <= 0) return 0;
   // just over a (cap + 1)-th of the CU's LDS, so that cap blocks fit and cap + 1 do not
   size_t b = (160u * 1024u) / (size_t)(cap + 1) + 1024u;
