@@ -55,10 +55,10 @@ __device__ __forceinline__ BlockXYZ node_block() {
   return b;
 }
 
-// The BF16 even step is compiled to issue all 46 loads before its first wait, where the
-// FP16 one issues 32, waits, then the rest; at the occupancy caps of even_step_lds that
-// keeps more bytes in flight than the step can use.  An empty asm that takes the 27 f
-// values makes the wavefront wait for them before it issues the g loads.  BF16 even step,
+// Left alone, the compiler has the BF16 even step issue all 46 loads before its first
+// wait, where the FP16 one issues 32, waits, then the rest; at the occupancy caps of
+// even_step_lds that keeps more bytes in flight than the step can use.  An empty asm that
+// takes the 27 f values makes the wavefront wait for them before it issues the g loads.  BF16 even step,
 // ms: 512^3 4.75 -> 4.50 (at FP16's 3 blocks per CU; with a cap of 2 and all loads first
 // 4.59-4.75), 256^3 0.548 -> 0.549.
 template <int MODE, int FLAGS, typename T, int QF>

@@ -77,7 +77,7 @@ inline bool ring_shape(const LaunchShape& sh, int n, size_t elem) {
 // add open streams.  Measured on gfx950 (D3Q27 x D3Q19 even step, ms): FP32 at 2 blocks
 // instead of 4, 256^3 1.137 -> 1.080, 384^3 4.02 -> 3.84, 512^3 9.26 -> 8.98 (3 blocks:
 // 1.131 at 256^3); 2-byte storage at 3 blocks instead of 4, 512^3 FP16 4.67 -> 4.42, BF16
-// 5.00 -> 4.92, while 256^3 and 128^3 lose with any cap.  The shifted odd step, whose
+// 5.00 -> 4.92 (before its loads were batched), while 256^3 and 128^3 lose with any cap.  The shifted odd step, whose
 // x-shifted lines neighbouring wavefronts share, gains nothing from a cap; the ring odd
 // step has its own (ring_step_lds).
 // The caps assume a step that issues its loads in two batches; the BF16 even step is made
