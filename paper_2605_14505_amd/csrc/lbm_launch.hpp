@@ -98,8 +98,8 @@ inline size_t even_step_lds(size_t elem, int n) {
 
 // Blocks resident per CU for the ring odd step (0 = as many as registers and its LDS
 // allow), counting the kernel's own LDS of `static_lds` bytes: FP32 at 2 (256^3 odd step
-// 1.103 -> 1.088 ms, 512^3 9.37 -> 9.22 against no cap); 2-byte storage lost with a cap
-// of 2 (256^3 0.553 -> 0.600) and keeps none.
+// 1.103 -> 1.088 ms, 512^3 9.37 -> 9.22 against no cap; at 3, 1.106); 2-byte storage lost
+// with a cap of 2 (256^3 0.553 -> 0.600), gained nothing at 3 or 4 (512^3), and keeps none.
 #ifndef STGV_ODD_CAP_FP32
 #define STGV_ODD_CAP_FP32 2
 #endif
